@@ -1,0 +1,128 @@
+"""Plain CPU oracle for the multi-moment vortex method (arXiv:1010.2475).
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the ``cpu_baseline`` leg of ``bench.py``; the product package never
+imports it.  The arithmetic lives in ``oracle.c`` (quad precision, the paper's
+appendix formulas term by term); this module only marshals numpy arrays.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile oracle.c with gcc (no GPU code involved)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src,
+                               "-lquadmath", "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_K.argtypes = [ctypes.c_int]
+        L.oracle_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
+                                 dp, dp, dp, dp]
+        L.oracle_rhs_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
+                                      dp, dp, ctypes.c_int, ip, ip, dp, dp]
+        L.oracle_rk4.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_long, dp, dp]
+        for f in (L.oracle_H_origin,):
+            f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+            f.restype = ctypes.c_double
+        L.oracle_HB.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double]
+        L.oracle_HB.restype = ctypes.c_double
+        L.oracle_gamma_tilde.argtypes = [ctypes.c_int] * 6 + [ctypes.c_double]
+        L.oracle_gamma_tilde.restype = ctypes.c_double
+        L.oracle_ck.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.oracle_ck.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def K_of(M):
+    return (M + 1) * (M + 2) // 2
+
+
+def rhs(M, nu, lambda0, t, x, mom):
+    """dx/dt [N,2] and dM/dt [N,K] at time t (all vortices, all coefficients)."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.ascontiguousarray(mom, dtype=np.float64).reshape(N, K_of(M))
+    dx = np.zeros_like(x)
+    dm = np.zeros_like(mom)
+    rc = lib().oracle_rhs(N, M, float(nu), _dp(lambda0), float(t), _dp(x), _dp(mom), _dp(dx), _dp(dm))
+    if rc != 0:
+        raise ValueError("oracle_rhs: invalid arguments")
+    return dx, dm
+
+
+def rhs_rows(M, nu, lambda0, t, x, mom, rows_j, rows_k):
+    """dM^j_k/dt for the listed (j, k) rows, and dx^j/dt of each listed row's vortex."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.ascontiguousarray(mom, dtype=np.float64).reshape(N, K_of(M))
+    rj = np.ascontiguousarray(rows_j, dtype=np.int32)
+    rk = np.ascontiguousarray(rows_k, dtype=np.int32)
+    out = np.zeros(len(rj))
+    outx = np.zeros((len(rj), 2))
+    rc = lib().oracle_rhs_rows(N, M, float(nu), _dp(lambda0), float(t), _dp(x), _dp(mom), len(rj),
+                               _ip(rj), _ip(rk), _dp(out), _dp(outx))
+    if rc != 0:
+        raise ValueError("oracle_rhs_rows: invalid arguments")
+    return out, outx
+
+
+def rk4(M, nu, lambda0, t0, dt, nsteps, x, mom):
+    """nsteps classic RK4 steps; returns new (x, mom) arrays."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.array(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.array(mom, dtype=np.float64).reshape(N, K_of(M))
+    rc = lib().oracle_rk4(N, M, float(nu), _dp(lambda0), float(t0), float(dt), int(nsteps),
+                          _dp(x), _dp(mom))
+    if rc != 0:
+        raise ValueError("oracle_rk4: invalid arguments")
+    return x, mom
+
+
+def H_origin(comp, a1, a2, Lam2):
+    return lib().oracle_H_origin(comp, a1, a2, Lam2)
+
+
+def HB(comp, a1, a2, s1, s2, Lam2):
+    return lib().oracle_HB(comp, a1, a2, s1, s2, Lam2)
+
+
+def gamma_tilde(k, l, m, lam):
+    return lib().oracle_gamma_tilde(k[0], k[1], l[0], l[1], m[0], m[1], lam)
+
+
+def ck(k, lam):
+    return lib().oracle_ck(k[0], k[1], lam)
