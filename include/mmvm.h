@@ -1,0 +1,140 @@
+/*
+ * mmvm.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * multi-moment vortex method (MMVM) of Uminsky, Wayne & Barbaro,
+ * "A multi-moment vortex method for 2D viscous fluids" (arXiv:1010.2475).
+ *
+ * The method represents the vorticity as N Gaussian vortices, each carrying
+ * Hermite moments M^j[k1,k2] up to total order M (eq:moment_expansion_def_tw0),
+ * and evolves them by the quadratic moment ODE of the appendix:
+ *   dM^j_k/dt = A + B + C              (eq:Final_CrossCoef)
+ *     A: self interaction              (eq:FinalSingleI, eq:FinalSingleII, eq:moment_evolutionFinish)
+ *     B: vortex-vortex interaction     (eq:FinalCrossI, eq:FinalCrossII)
+ *     C: drift of the centre           (eq:last_termsimp)
+ *   dx^j/dt                            (eq:xjdot_Final)
+ * with core scales lambda_j(t)^2 = lambda_{j,0}^2 + 4 nu t (eq:phi00).
+ *
+ * Conventions shared by every entry point
+ *  - Moments are stored shell-major: total order s = k1+k2 = 0..M, then k2
+ *    ascending; index(k1,k2) = s(s+1)/2 + k2; K = (M+1)(M+2)/2 per vortex.
+ *    mom is [n][K] row-major float64, x is [n][2] float64 (centres).
+ *  - Readings of the paper fixed by this library: the pair term carries the
+ *    target's moments on the binomial index l and the source's on the velocity
+ *    index m; s_{j,j'} = x^j - x^{j'}; the centre velocity sums j' != j; every
+ *    sum is truncated at total order <= M; vortex j uses its own lambda_j and
+ *    a pair (j, j') uses Lambda^2 = lambda_j^2 + lambda_{j'}^2 in the kernel H^B.
+ *  - Every function returns an mmvm_status and never throws across the ABI.
+ *    Asynchronous entry points do not synchronise; an error found on the
+ *    device (zero circulation, non-finite state) is latched and returned by
+ *    mmvm_sync() or mmvm_poll().
+ *  - The caller owns every buffer passed in.  The library owns only its
+ *    internal workspaces and tables (device memory, cached per device and
+ *    stream and grown on demand) and server slots.
+ */
+#ifndef MMVM_H
+#define MMVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MMVM_OK = 0,
+    MMVM_PENDING = 1,     /* mmvm_poll: request not finished yet */
+    MMVM_EINVAL = -1,     /* bad pointer, size, nu < 0, lambda0 <= 0, dt or nsteps invalid */
+    MMVM_ENOMEM = -2,     /* device or host allocation failed */
+    MMVM_EORDER = -3,     /* n < 1, order < 0 or order > MMVM_MAX_ORDER */
+    MMVM_EZEROCIRC = -4,  /* a vortex of a multi-vortex problem has M^j_00 == 0 (eq:mass) */
+    MMVM_EDEVICE = -5,    /* HIP runtime error */
+    MMVM_ENOTFOUND = -6,  /* unknown ticket */
+    MMVM_EBUDGET = -7,    /* request footprint exceeds the server's HBM budget */
+    MMVM_ENONFINITE = -8  /* NaN/Inf in the state */
+} mmvm_status;
+
+typedef enum {
+    MMVM_FP64 = 0,  /* FP64 everywhere; double-double for the self contraction at high order */
+    MMVM_MIXED = 1  /* FP32 pair interaction and FP64 self contraction; FP64 state and tables */
+} mmvm_precision;
+
+#define MMVM_MAX_ORDER 40
+
+/* One solve: n vortices of maximum total order `order`, viscosity nu = 1/Re,
+ * initial core scales lambda0[n] (HOST pointer, all > 0). */
+typedef struct {
+    int32_t n;
+    int32_t order;
+    double nu;
+    const double* lambda0;
+} mmvm_problem;
+
+/* ---------------------------------------------------------------------------
+ * Coefficient tables (host).  kind:
+ *   MMVM_TABLE_H        H_1 and H_2 of the appendix (derivatives of the two
+ *                       velocity components of a Gaussian of squared width 2,
+ *                       i.e. lambda = 1, at the origin) for total order
+ *                       <= 3*order+1: double[2][T], T = (3*order+2)(3*order+3)/2,
+ *                       shell-major like the moments.
+ *   MMVM_TABLE_FACTORS  the lambda-free factors of eq:FinalSingleI/II:
+ *                       f0[k][l][i] = C(l,i) 2^i k!/(k-i)! and
+ *                       f1[k][l][i] = C(l,i) 2^{i+1} k!/(k-i-1)! (zero outside
+ *                       their ranges): double[2][order+1][order+1][order+1].
+ * With out == NULL only *needed_bytes is set.  MMVM_EINVAL if out_bytes is too
+ * small or kind is unknown. */
+#define MMVM_TABLE_H 0
+#define MMVM_TABLE_FACTORS 1
+mmvm_status mmvm_coeffs(int32_t order, int32_t kind, void* out, size_t out_bytes, size_t* needed_bytes);
+
+/* ---------------------------------------------------------------------------
+ * One right-hand side at time t (eq:Final_CrossCoef, eq:xjdot_Final):
+ * x[n][2], mom[n][K] in, dx[n][2], dmom[n][K] out.  All four are DEVICE
+ * pointers owned by the caller; stream is a hipStream_t (NULL = default
+ * stream).  Asynchronous; dmom[:,0] is exactly 0 (circulation). */
+mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const double* mom,
+                     double* dx, double* dmom, mmvm_precision prec, void* stream);
+
+/* nsteps classic RK4 steps (c = 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6)
+ * of size dt from t0, in place on the DEVICE arrays x and mom.  Asynchronous,
+ * stream-ordered. */
+mmvm_status mmvm_step(const mmvm_problem* prob, double t0, double dt, int64_t nsteps, double* x,
+                      double* mom, mmvm_precision prec, void* stream);
+
+/* Waits for `stream` and returns (and clears) any error latched by device-side
+ * checks of earlier calls on it: MMVM_EZEROCIRC or MMVM_ENONFINITE. */
+mmvm_status mmvm_sync(void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching solve server on the current device.
+ * The server owns device memory up to hbm_budget_bytes and at most max_slots
+ * resident requests.  mmvm_submit copies the HOST initial state (x0[n][2],
+ * mom0[n][K], prob->lambda0) and returns at once with a ticket; requests are
+ * admitted when a slot and their HBM footprint are free, run together with the
+ * other resident requests step by step, and leave at completion.  Thread-safe.
+ * The result of a request does not depend on what else is resident. */
+typedef struct mmvm_server mmvm_server;
+typedef struct {
+    double t_arrive, t_admit, t_start, t_done; /* seconds, server clock */
+    int64_t steps;
+} mmvm_stats;
+
+mmvm_status mmvm_server_create(size_t hbm_budget_bytes, int32_t max_slots, mmvm_server** out);
+mmvm_status mmvm_submit(mmvm_server* srv, const mmvm_problem* prob, double t0, double dt,
+                        int64_t nsteps, const double* x0, const double* mom0, mmvm_precision prec,
+                        uint64_t* ticket);
+/* MMVM_PENDING until done; then copies the final state into caller-owned HOST
+ * buffers x_out[n][2], mom_out[n][K] (either may be NULL), fills *stats if
+ * non-NULL, frees the slot and forgets the ticket. */
+mmvm_status mmvm_poll(mmvm_server* srv, uint64_t ticket, double* x_out, double* mom_out,
+                      mmvm_stats* stats);
+/* Blocks until every submitted request has finished (results stay pollable). */
+mmvm_status mmvm_server_drain(mmvm_server* srv);
+mmvm_status mmvm_server_destroy(mmvm_server* srv);
+
+/* Human-readable name of a status code (static string). */
+const char* mmvm_status_string(mmvm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMVM_H */

@@ -1,0 +1,346 @@
+// C ABI of libmmvm (declarations and contracts in include/mmvm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/mmvm.h"
+#include "api_internal.hpp"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+namespace mmvm {
+
+// ---------------------------------------------------------------------------
+// device tables (per device, per order)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevTablesOwner {
+    DevTables t;
+    std::vector<void*> bufs;
+    ~DevTablesOwner()
+    {
+        for (void* p : bufs) (void)hipFree(p);
+    }
+};
+
+std::mutex g_tab_mu;
+std::map<std::pair<int, int>, std::unique_ptr<DevTablesOwner>> g_dev_tables;
+
+template <typename V>
+const double* upload(DevTablesOwner& o, const V& v, hipError_t& err)
+{
+    if (err != hipSuccess) return nullptr;
+    void* p = nullptr;
+    size_t n = v.size() * sizeof(double);
+    if (n == 0) n = sizeof(double);
+    err = hipMalloc(&p, n);
+    if (err != hipSuccess) return nullptr;
+    o.bufs.push_back(p);
+    if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    return (const double*)p;
+}
+
+}  // namespace
+
+mmvm_status device_tables(int M, const DevTables** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MMVM_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto key = std::make_pair(dev, M);
+    auto it = g_dev_tables.find(key);
+    if (it != g_dev_tables.end()) {
+        *out = &it->second->t;
+        return MMVM_OK;
+    }
+    const Tables& H = get_tables(M);
+    std::unique_ptr<DevTablesOwner> o(new DevTablesOwner());
+    hipError_t err = hipSuccess;
+    DevTables& d = o->t;
+    d.M = H.M; d.K = H.K; d.P = H.P; d.GM = H.GM; d.KG = H.KG; d.T0N = H.T0N;
+    d.t0_hi = upload(*o, H.t0_hi, err);
+    d.t0_lo = upload(*o, H.t0_lo, err);
+    d.f0_hi = upload(*o, H.f0_hi, err);
+    d.f0_lo = upload(*o, H.f0_lo, err);
+    d.f1_hi = upload(*o, H.f1_hi, err);
+    d.f1_lo = upload(*o, H.f1_lo, err);
+    d.c1_hi = upload(*o, H.c1_hi, err);
+    d.c1_lo = upload(*o, H.c1_lo, err);
+    d.kap0 = upload(*o, H.kap0, err);
+    d.kap1 = upload(*o, H.kap1, err);
+    d.hol = upload(*o, H.hol, err);
+    if (err != hipSuccess) return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+    *out = &o->t;
+    g_dev_tables[key] = std::move(o);
+    return MMVM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces (per device and stream), grown on demand
+// ---------------------------------------------------------------------------
+void Workspace::release()
+{
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    bytes = 0;
+}
+
+mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
+{
+    const int K = (M_ + 1) * (M_ + 2) / 2;
+    const int GM = M_ == 0 ? 1 : 2 * M_;
+    const int KG = (GM + 1) * (GM + 2) / 2;
+    size_t need = 0;
+    auto add = [&](size_t n) {
+        size_t o = need;
+        need += (n + 63) & ~(size_t)63;
+        return o;
+    };
+    size_t o_flag = add(sizeof(int) * 16);  // first: fixed offset across layouts
+    size_t o_lam0 = add(sizeof(double) * N_);
+    size_t o_xs = add(sizeof(double) * 2 * N_);
+    size_t o_ys = add(sizeof(double) * (size_t)N_ * K);
+    size_t o_accx = add(sizeof(double) * 2 * N_);
+    size_t o_accm = add(sizeof(double) * (size_t)N_ * K);
+    size_t o_lam2 = add(sizeof(double) * N_);
+    size_t o_alpha = add(sizeof(double) * (size_t)N_ * K);
+    size_t o_alphaT = add(sizeof(double) * (size_t)N_ * K);
+    size_t o_alphaT32 = add(sizeof(float) * (size_t)N_ * K);
+    size_t o_sself = add(sizeof(double) * (size_t)N_ * KG);
+    size_t o_sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
+    size_t o_spair = add(sizeof(double) * (size_t)N_ * KG);
+    if (need > bytes) {
+        // the old buffer may still be used by queued work on this stream
+        if (base) {
+            if (hipStreamSynchronize(st) != hipSuccess) return MMVM_EDEVICE;
+            // keep a latched error across the reallocation
+            int f = 0;
+            (void)hipMemcpy(&f, flag_ptr, sizeof(int), hipMemcpyDeviceToHost);
+            latched |= f;
+            release();
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, need);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+        base = (char*)p;
+        bytes = need;
+        if (hipMemset(base + o_flag, 0, sizeof(int) * 16) != hipSuccess) return MMVM_EDEVICE;
+        lam0_cache.clear();
+    }
+    N = N_;
+    M = M_;
+    char* b = base;
+    bufs.N = N_;
+    bufs.lam0sq = (const double*)(b + o_lam0);
+    bufs.xs = (double*)(b + o_xs);
+    bufs.ys = (double*)(b + o_ys);
+    bufs.accx = (double*)(b + o_accx);
+    bufs.accm = (double*)(b + o_accm);
+    bufs.lam2 = (double*)(b + o_lam2);
+    bufs.alpha = (double*)(b + o_alpha);
+    bufs.alphaT = (double*)(b + o_alphaT);
+    bufs.alphaT32 = (float*)(b + o_alphaT32);
+    bufs.s_self = (double*)(b + o_sself);
+    bufs.s_self_lo = need_dd ? (double*)(b + o_sselflo) : nullptr;
+    bufs.s_pair = (double*)(b + o_spair);
+    bufs.flag = (int*)(b + o_flag);
+    flag_ptr = bufs.flag;
+    lam0_dev = (double*)(b + o_lam0);
+    return MMVM_OK;
+}
+
+mmvm_status Workspace::set_lambda0(const double* lambda0, int N_, hipStream_t st)
+{
+    std::vector<double> sq(N_);
+    for (int j = 0; j < N_; ++j) sq[j] = lambda0[j] * lambda0[j];
+    if (sq == lam0_cache) return MMVM_OK;
+    // the device copy may be read by queued work; order the update on the stream
+    if (hipMemcpyAsync(lam0_dev, sq.data(), sizeof(double) * N_, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MMVM_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return MMVM_EDEVICE;
+    lam0_cache.swap(sq);
+    return MMVM_OK;
+}
+
+namespace {
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+}  // namespace
+
+Workspace* workspace_for(hipStream_t st)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto& w = g_ws[std::make_pair(dev, st)];
+    if (!w) w.reset(new Workspace());
+    return w.get();
+}
+
+mmvm_status validate(const mmvm_problem* prob)
+{
+    if (!prob) return MMVM_EINVAL;
+    if (prob->n < 1 || prob->order < 0 || prob->order > MMVM_MAX_ORDER) return MMVM_EORDER;
+    if (!(prob->nu >= 0.0) || !std::isfinite(prob->nu) || !prob->lambda0) return MMVM_EINVAL;
+    for (int j = 0; j < prob->n; ++j)
+        if (!(prob->lambda0[j] > 0.0) || !std::isfinite(prob->lambda0[j])) return MMVM_EINVAL;
+    if (prob->n > 1 && !pair_order_supported(prob->order)) return MMVM_EORDER;
+    return MMVM_OK;
+}
+
+bool use_dd(int M, mmvm_precision prec) { return prec == MMVM_FP64 && M > kDDThreshold; }
+
+static mmvm_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return MMVM_OK;
+    return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+}
+
+// one right-hand side on the stage input (xin, min_) at time t
+mmvm_status run_rhs_core(const DevTables& T, Workspace& W, const double* xin, const double* min_, double t,
+                         double nu, mmvm_precision prec, const StageArgs& A, hipStream_t st)
+{
+    const bool pair = W.bufs.N > 1;
+    const bool f32 = prec == MMVM_MIXED;
+    const bool dd = use_dd(T.M, prec);
+    hipError_t e = launch_prep(T, W.bufs, xin, min_, t, nu, pair, f32, st);
+    if (e == hipSuccess) e = launch_self(T, W.bufs, dd, st);
+    if (e == hipSuccess && pair) e = launch_pair(T, W.bufs, f32, 1, st);
+    if (e == hipSuccess) e = launch_stage2(T, W.bufs, A, dd, st);
+    return hip_status(e);
+}
+
+}  // namespace mmvm
+
+using namespace mmvm;
+
+extern "C" {
+
+const char* mmvm_status_string(mmvm_status s)
+{
+    switch (s) {
+    case MMVM_OK: return "MMVM_OK";
+    case MMVM_PENDING: return "MMVM_PENDING";
+    case MMVM_EINVAL: return "MMVM_EINVAL";
+    case MMVM_ENOMEM: return "MMVM_ENOMEM";
+    case MMVM_EORDER: return "MMVM_EORDER";
+    case MMVM_EZEROCIRC: return "MMVM_EZEROCIRC";
+    case MMVM_EDEVICE: return "MMVM_EDEVICE";
+    case MMVM_ENOTFOUND: return "MMVM_ENOTFOUND";
+    case MMVM_EBUDGET: return "MMVM_EBUDGET";
+    case MMVM_ENONFINITE: return "MMVM_ENONFINITE";
+    }
+    return "unknown";
+}
+
+mmvm_status mmvm_coeffs(int32_t order, int32_t kind, void* out, size_t out_bytes, size_t* needed_bytes)
+{
+    if (order < 0 || order > MMVM_MAX_ORDER) return MMVM_EORDER;
+    const Tables& T = get_tables(order);
+    size_t need = 0;
+    if (kind == MMVM_TABLE_H) {
+        int nmax = 3 * order + 1;
+        size_t cnt = (size_t)(nmax + 1) * (nmax + 2) / 2;
+        need = 2 * cnt * sizeof(double);
+        if (needed_bytes) *needed_bytes = need;
+        if (!out) return MMVM_OK;
+        if (out_bytes < need) return MMVM_EINVAL;
+        double* o = (double*)out;
+        // H_1(a) = -Psi0(a + e2), H_2(a) = Psi0(a + e1), Psi0 nonzero only even-even
+        for (int s = 0; s <= nmax; ++s)
+            for (int a2 = 0; a2 <= s; ++a2) {
+                int a1 = s - a2;
+                size_t i = (size_t)tri(a1, a2);
+                double h1 = 0.0, h2 = 0.0;
+                if (a1 % 2 == 0 && a2 % 2 == 1) h1 = -T.t0_hi[tri(a1 / 2, (a2 + 1) / 2)];
+                if (a1 % 2 == 1 && a2 % 2 == 0) h2 = T.t0_hi[tri((a1 + 1) / 2, a2 / 2)];
+                o[i] = h1;
+                o[cnt + i] = h2;
+            }
+        return MMVM_OK;
+    }
+    if (kind == MMVM_TABLE_FACTORS) {
+        size_t cnt = (size_t)(order + 1) * (order + 1) * (order + 1);
+        need = 2 * cnt * sizeof(double);
+        if (needed_bytes) *needed_bytes = need;
+        if (!out) return MMVM_OK;
+        if (out_bytes < need) return MMVM_EINVAL;
+        double* o = (double*)out;
+        std::memcpy(o, T.f0_hi.data(), cnt * sizeof(double));
+        std::memcpy(o + cnt, T.f1_hi.data(), cnt * sizeof(double));
+        return MMVM_OK;
+    }
+    return MMVM_EINVAL;
+}
+
+mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const double* mom, double* dx,
+                     double* dmom, mmvm_precision prec, void* stream)
+{
+    mmvm_status s = validate(prob);
+    if (s != MMVM_OK) return s;
+    if (!x || !mom || !dx || !dmom || !std::isfinite(t)) return MMVM_EINVAL;
+    if (prec != MMVM_FP64 && prec != MMVM_MIXED) return MMVM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables* T = nullptr;
+    if ((s = device_tables(prob->order, &T)) != MMVM_OK) return s;
+    Workspace* W = workspace_for(st);
+    if (!W) return MMVM_EDEVICE;
+    std::lock_guard<std::mutex> lk(W->mu);
+    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), st)) != MMVM_OK) return s;
+    if ((s = W->set_lambda0(prob->lambda0, prob->n, st)) != MMVM_OK) return s;
+    StageArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.mode = MODE_RHS;
+    A.t_stage = t;
+    A.nu = prob->nu;
+    A.dx = dx;
+    A.dmom = dmom;
+    return run_rhs_core(*T, *W, x, mom, t, prob->nu, prec, A, st);
+}
+
+mmvm_status mmvm_step(const mmvm_problem* prob, double t0, double dt, int64_t nsteps, double* x, double* mom,
+                      mmvm_precision prec, void* stream)
+{
+    mmvm_status s = validate(prob);
+    if (s != MMVM_OK) return s;
+    if (!x || !mom || nsteps < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return MMVM_EINVAL;
+    if (prec != MMVM_FP64 && prec != MMVM_MIXED) return MMVM_EINVAL;
+    if (nsteps == 0) return MMVM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables* T = nullptr;
+    if ((s = device_tables(prob->order, &T)) != MMVM_OK) return s;
+    Workspace* W = workspace_for(st);
+    if (!W) return MMVM_EDEVICE;
+    std::lock_guard<std::mutex> lk(W->mu);
+    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), st)) != MMVM_OK) return s;
+    if ((s = W->set_lambda0(prob->lambda0, prob->n, st)) != MMVM_OK) return s;
+    return run_steps(*T, *W, prob->nu, t0, dt, nsteps, x, mom, prec, st);
+}
+
+mmvm_status mmvm_sync(void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return MMVM_EDEVICE;
+    Workspace* W = workspace_for(st);
+    if (!W) return MMVM_EDEVICE;
+    std::lock_guard<std::mutex> lk(W->mu);
+    int f = W->latched;
+    W->latched = 0;
+    if (W->flag_ptr) {
+        int d = 0;
+        if (hipMemcpy(&d, W->flag_ptr, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return MMVM_EDEVICE;
+        f |= d;
+        if (d && hipMemset(W->flag_ptr, 0, sizeof(int)) != hipSuccess) return MMVM_EDEVICE;
+    }
+    if (f & 1) return MMVM_EZEROCIRC;
+    if (f & 2) return MMVM_ENONFINITE;
+    return MMVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// Pair-interaction kernel, templated on the order M (included by one
+// translation unit per order, so that the fully unrolled variants compile in
+// parallel).
+#pragma once
+#include <type_traits>
+#include <utility>
+
+#include "kernels.hpp"
+#include "util.hpp"
+
+namespace mmvm {
+
+// ---------------------------------------------------------------------------
+// pair velocity-derivative table.
+//
+// For target j and source j' with c = lambda_j^2 + lambda_{j'}^2 and
+// s = (x^j - x^{j'}) / sqrt(c), the derivatives D^a psi of the stream
+// function psi(s) = (ln|s|^2 + E1(|s|^2)) / (4 pi) (velocity V00 = (-d2 psi, d1 psi)
+// of a unit Gaussian) are generated shell by shell n = |a| = 1..P:
+//   * the two edges a = (0, n), (1, n-1) from the complex derivative
+//     psi_{n0} = (-1)^{n-1} (n-1)! P(n, w) / (4 pi z^n),   w = |s|^2,
+//     written (-1)^{n-1}(n-1)!/(4pi) g_n zbar^n with g_n = P(n,w)/w^n obtained
+//     by the stable downward recurrence g_n = w g_{n+1} + e^{-w}/n!, plus the
+//     kappa-weighted products of 1-D Gaussian derivatives h_c(s1) h_d(s2);
+//   * the rest of the shell by the Laplacian relation
+//     Psi(a1+2, a2) = h_{a1}(s1) h_{a2}(s2) / pi - Psi(a1, a2+2).
+// Each shell is consumed at once by the Hankel contraction
+//   S[g] += sum_m alpha'_m Psi'(m + g),
+// alpha'_m = alpha^{j'}_m (lambda_{j'}/lambda_j)^{|m|}, Psi' = (lambda_j/sqrt(c))^{|a|} Psi,
+// which is D^g of the source's velocity smoothed by the target Gaussian, in
+// the target's lambda units.
+// ---------------------------------------------------------------------------
+template <int M, typename R>
+__global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ xs, const double* __restrict__ lam2,
+                                              const R* __restrict__ aT, const double* __restrict__ kap0,
+                                              const double* __restrict__ kap1, const double* __restrict__ hol,
+                                              double* __restrict__ spair)
+{
+    constexpr int K = (M + 1) * (M + 2) / 2;
+    constexpr int P = M == 0 ? 1 : 3 * M;
+    constexpr int GM = M == 0 ? 1 : 2 * M;
+    constexpr int KG = (GM + 1) * (GM + 2) / 2;
+    constexpr int HN = P >= 2 ? P - 1 : 1;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    constexpr double kInvPi = 0.318309886183790671537767526745;
+
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (j >= N) return;  // uniform per wavefront
+
+    const double xj1 = xs[2 * j], xj2 = xs[2 * j + 1], lj2 = lam2[j];
+    const double ilj = 1.0 / sqrt(lj2);
+    const double lj = lj2 * ilj;
+
+    double acc[KG];
+    R acc32[F32 ? KG : 1];
+    sfor<0, KG>([&](auto g) { acc[g] = 0.0; });
+    if constexpr (F32) sfor<0, KG>([&](auto g) { acc32[g] = 0.0f; });
+    int pending = 0;
+
+    for (int jp = lane; jp < N; jp += 64) {
+        if (jp == j) continue;
+        const double lp2 = lam2[jp];
+        const double c = lj2 + lp2;
+        const double isc = 1.0 / sqrt(c);
+        const double s1 = (xj1 - xs[2 * jp]) * isc, s2 = (xj2 - xs[2 * jp + 1]) * isc;
+        const double w = s1 * s1 + s2 * s2;
+        const double e1 = exp(-s1 * s1), e2 = exp(-s2 * s2);
+        const double E = e1 * e2;
+
+        // g_n = P(n, w) / w^n, n = 1..P
+        double gsr[P + 1];
+        {
+            double ifP = 1.0;
+            for (int f = 2; f <= P; ++f) ifP /= (double)f;
+            double gP;
+            if (w <= (double)P) {
+                double term = ifP, sum = 0.0;
+                for (int k = 0; k < 400; ++k) {
+                    sum += term;
+                    term *= w / (double)(P + k + 1);
+                    if (term < 1e-17 * sum) break;
+                }
+                gP = E * sum;
+            } else {
+                double sm = 0.0, term = 1.0, wp = 1.0;
+                for (int k = 0; k < P; ++k) {
+                    sm += term;
+                    term *= w / (double)(k + 1);
+                    wp *= w;
+                }
+                gP = (1.0 - E * sm) / wp;
+            }
+            gsr[P] = gP;
+            double ifn = ifP;
+            sfor<1, P>([&](auto q) {
+                constexpr int n = P - q;  // P-1 .. 1
+                ifn *= (double)(n + 1);   // 1/n!
+                gsr[n] = w * gsr[n + 1] + E * ifn;
+            });
+        }
+
+        // 1-D Gaussian derivatives h_a(x) = d^a/dx^a exp(-x^2)
+        R h1[HN], h2[HN];
+        h1[0] = (R)e1;
+        h2[0] = (R)e2;
+        if constexpr (HN > 1) {
+            h1[1] = (R)(-2.0 * s1) * h1[0];
+            h2[1] = (R)(-2.0 * s2) * h2[0];
+        }
+        sfor<1, HN - 1>([&](auto a) {
+            h1[a + 1] = (R)(-2.0 * s1) * h1[a] - (R)(2 * a) * h1[a - 1];
+            h2[a + 1] = (R)(-2.0 * s2) * h2[a] - (R)(2 * a) * h2[a - 1];
+        });
+
+        // scaled source moments
+        R am[K];
+        {
+            const R ratio = (R)(sqrt(lp2) * ilj);
+            R rp = (R)1;
+            sfor<0, M + 1>([&](auto s) {
+                sfor<0, s + 1>([&](auto m2) {
+                    constexpr int idx = ctri(s - m2, m2);
+                    am[idx] = aT[(long)idx * N + jp] * rp;
+                });
+                rp *= ratio;
+            });
+        }
+
+        const R tau = (R)(lj * isc);
+        R tn = (R)1;
+        double zr = 1.0, zi = 0.0;
+        sfor<1, P + 1>([&](auto nc) {
+            constexpr int n = nc;
+            // zbar^n
+            {
+                double nr = zr * s1 + zi * s2;  // (zr + i zi)(s1 - i s2)
+                double ni = zi * s1 - zr * s2;
+                zr = nr;
+                zi = ni;
+            }
+            const double hr = hol[n] * gsr[n] * zr, hi = hol[n] * gsr[n] * zi;
+            // 2 Re(i^n h), 2 Re(i^{n-1} h)
+            double e0, e1v;
+            if constexpr (n % 4 == 0) { e0 = hr; e1v = hi; }
+            else if constexpr (n % 4 == 1) { e0 = -hi; e1v = hr; }
+            else if constexpr (n % 4 == 2) { e0 = -hr; e1v = -hi; }
+            else { e0 = hi; e1v = -hr; }
+            R psi[n + 1];
+            R p0 = (R)(2.0 * e0), p1 = (R)(2.0 * e1v);
+            R prod[n >= 2 ? n - 1 : 1];
+            if constexpr (n >= 2) {
+                sfor<0, n - 1>([&](auto cc) {
+                    prod[cc] = h1[cc] * h2[n - 2 - cc];
+                    p0 += (R)kap0[n * (P + 1) + cc] * prod[cc];
+                    p1 += (R)kap1[n * (P + 1) + cc] * prod[cc];
+                });
+            }
+            psi[0] = p0;
+            psi[1] = p1;
+            if constexpr (n >= 2) {
+                sfor<0, n - 1>([&](auto a) { psi[a + 2] = prod[a] * (R)kInvPi - psi[a]; });
+            }
+            tn *= tau;
+            sfor<0, n + 1>([&](auto a) { psi[a] *= tn; });
+            // Hankel contraction of this shell
+            sfor<0, n + 1>([&](auto a) {
+                constexpr int m1max = a < M ? (int)a : M;
+                sfor<0, m1max + 1>([&](auto m1) {
+                    constexpr int rem = M - m1;
+                    constexpr int m2max = (n - a) < rem ? (n - a) : rem;
+                    sfor<0, m2max + 1>([&](auto m2) {
+                        constexpr int g1 = a - m1, g2 = n - a - m2;
+                        if constexpr (g1 + g2 >= 1 && g1 + g2 <= GM) {
+                            if constexpr (F32)
+                                acc32[ctri(g1, g2)] += am[ctri(m1, m2)] * psi[a];
+                            else
+                                acc[ctri(g1, g2)] = fma(am[ctri(m1, m2)], psi[a], acc[ctri(g1, g2)]);
+                        }
+                    });
+                });
+            });
+        });
+        if constexpr (F32) {
+            if (++pending == 8) {
+                sfor<0, KG>([&](auto g) { acc[g] += (double)acc32[g]; acc32[g] = 0.0f; });
+                pending = 0;
+            }
+        }
+    }
+    if constexpr (F32) sfor<0, KG>([&](auto g) { acc[g] += (double)acc32[g]; });
+
+    // wavefront reduction over the sources held by the 64 lanes
+    sfor<1, KG>([&](auto g) {
+        double v = acc[g];
+        v += __shfl_xor(v, 32, 64);
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 8, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 1, 64);
+        if (lane == (g & 63)) spair[(long)j * KG + g] = v;
+    });
+    if (lane == 0) spair[(long)j * KG] = 0.0;
+}
+
+template <int M>
+hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, bool f32, hipStream_t st)
+{
+    const int wpb = 4;
+    dim3 grid((B.N + wpb - 1) / wpb);
+    if (f32)
+        hipLaunchKernelGGL((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2, B.alphaT32, T.kap0,
+                           T.kap1, T.hol, B.s_pair);
+    else
+        hipLaunchKernelGGL((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2, B.alphaT, T.kap0,
+                           T.kap1, T.hol, B.s_pair);
+    return hipGetLastError();
+}
+
+}  // namespace mmvm

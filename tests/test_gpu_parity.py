@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error metric (per vortex, orthonormal Hermite coefficients n_k M_k with
+n_k = sqrt(2^{|k|} k1! k2!) / lambda_j^{|k|}):  max_k |d(n_k M_k)| / max_k |n_k M_k|,
+maximised over vortices; positions: max |dx| / max(1, max |x|).
+Bars: FP64 1e-12; mixed (FP32 pair interaction) 1e-6; circulation exact."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1010_2475_amd import mmvm
+    mmvm.lib()
+    return torch, mmvm
+
+
+def _nk(M, lam):
+    from paper_1010_2475_amd import workloads as wl
+    return wl.orthonormal_scale(M, lam)
+
+
+def normwise(M, lam_t, ref, got):
+    worst = 0.0
+    for j in range(ref.shape[0]):
+        n = _nk(M, lam_t[j])
+        den = np.abs(ref[j] * n).max()
+        num = np.abs((got[j] - ref[j]) * n).max()
+        worst = max(worst, num / den if den > 0 else num)
+    return worst
+
+
+def gpu_rhs(env, w, t, prec, x=None, mom=None):
+    torch, mm = env
+    x = w.x if x is None else x
+    mom = w.mom if mom is None else mom
+    dev = torch.device("cuda:0")
+    X = torch.tensor(x, dtype=torch.float64, device=dev).contiguous()
+    Mo = torch.tensor(mom, dtype=torch.float64, device=dev).contiguous()
+    dX = torch.zeros_like(X)
+    dM = torch.zeros_like(Mo)
+    print("gpu_rhs N=%d M=%d prec=%d" % (w.N, w.M, prec), flush=True)
+    mm.rhs(w.M, w.nu, w.lam0, t, X, Mo, dX, dM, prec)
+    mm.sync()
+    return dX.cpu().numpy(), dM.cpu().numpy()
+
+
+def gpu_step(env, w, t0, nsteps, prec):
+    torch, mm = env
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.x, dtype=torch.float64, device=dev).contiguous()
+    Mo = torch.tensor(w.mom, dtype=torch.float64, device=dev).contiguous()
+    print("gpu_step N=%d M=%d steps=%d prec=%d" % (w.N, w.M, nsteps, prec), flush=True)
+    mm.step(w.M, w.nu, w.lam0, t0, w.dt, nsteps, X, Mo, prec)
+    mm.sync()
+    return X.cpu().numpy(), Mo.cpu().numpy()
+
+
+def rand_workload(seed, N, M, amp=0.08, spread=1.5):
+    from paper_1010_2475_amd import workloads as wl
+    rng = np.random.default_rng(seed)
+    K = wl.K_of(M)
+    x = rng.uniform(-spread, spread, (N, 2))
+    mom = rng.normal(0.0, amp, (N, K))
+    mom[:, 0] = rng.uniform(0.4, 1.0, N) * rng.choice([-1, 1], N)
+    if M >= 1:
+        mom[:, 1:3] = 0.0
+    lam0 = rng.uniform(0.3, 0.7, N)
+    return wl.Workload("rand", M, x, mom, lam0, 0.005, 1e-3, 10)
+
+
+# ---------------------------------------------------------------------------
+# right-hand side, small cases covering several tiles, ragged tails and edges
+# ---------------------------------------------------------------------------
+CASES = [(1, 0), (1, 1), (1, 3), (1, 10), (2, 0), (2, 2), (3, 4), (5, 6), (67, 2), (130, 3)]
+
+
+@pytest.mark.parametrize("N,M", CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rhs_matches_oracle(env, orc, N, M, prec):
+    w = rand_workload(100 + 7 * N + M, N, M)
+    t = 0.37
+    if N <= 5 or M <= 2:
+        dx_r, dm_r = orc.rhs(M, w.nu, w.lam0, t, w.x, w.mom)
+        rows = None
+    else:  # sample targets for the larger cases
+        js = [0, N // 2, N - 1]
+        rj = [j for j in js for _ in range(w.K)]
+        rk = [k for _ in js for k in range(w.K)]
+        d, dxr = orc.rhs_rows(M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+        dm_r = d.reshape(len(js), w.K)
+        dx_r = dxr.reshape(len(js), w.K, 2)[:, 0, :]
+        rows = js
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    if rows is not None:
+        dx_g, dm_g, lam_t = dx_g[rows], dm_g[rows], lam_t[rows]
+    tol = FP64_TOL if prec == 0 else MIXED_TOL
+    assert np.all(dm_g[:, 0] == 0.0)
+    assert normwise(M, lam_t, dm_r, dm_g) <= tol
+    if N > 1:
+        assert np.abs(dx_g - dx_r).max() <= tol * max(1.0, np.abs(dx_r).max())
+    else:
+        assert np.all(dx_g == 0.0)
+
+
+def test_rhs_zero_order_two_vortices_closed_form(env):
+    """Order 0: xdot^j = Gamma_{j'} V00(x^j - x^{j'}; lambda_j^2 + lambda_{j'}^2)."""
+    from paper_1010_2475_amd import workloads as wl
+    x = np.array([[-0.6, 0.1], [0.5, -0.2]])
+    mom = np.array([[0.8], [1.3]])
+    w = wl.Workload("pair0", 0, x, mom, [0.3, 0.45], 1e-3, 1e-3, 1)
+    dx, dm = gpu_rhs(env, w, 2.0, 0)
+    lam2 = w.lam0 ** 2 + 4 * w.nu * 2.0
+    for j, jp in ((0, 1), (1, 0)):
+        s = x[j] - x[jp]
+        r2 = s @ s
+        v = mom[jp, 0] * np.array([-s[1], s[0]]) * (1 - math.exp(-r2 / (lam2[0] + lam2[1]))) / (2 * math.pi * r2)
+        assert np.abs(dx[j] - v).max() <= 1e-15
+    assert np.all(dm == 0.0)
+
+
+def test_rhs_deterministic(env):
+    w = rand_workload(5, 40, 4)
+    a = gpu_rhs(env, w, 0.1, 0)
+    b = gpu_rhs(env, w, 0.1, 0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_zero_circulation_is_reported(env):
+    torch, mm = env
+    w = rand_workload(9, 3, 2)
+    w.mom[1, 0] = 0.0
+    X = torch.tensor(w.x, device="cuda:0")
+    Mo = torch.tensor(w.mom, device="cuda:0")
+    dX, dM = torch.zeros_like(X), torch.zeros_like(Mo)
+    mm.rhs(w.M, w.nu, w.lam0, 0.0, X, Mo, dX, dM, 0)
+    with pytest.raises(mm.MMVMError) as e:
+        mm.sync()
+    assert e.value.status == -4
+    mm.sync()  # cleared
+
+
+def test_nonfinite_is_reported(env):
+    torch, mm = env
+    w = rand_workload(10, 1, 3)
+    w.mom[0, 4] = float("nan")
+    X = torch.tensor(w.x, device="cuda:0")
+    Mo = torch.tensor(w.mom, device="cuda:0")
+    dX, dM = torch.zeros_like(X), torch.zeros_like(Mo)
+    mm.rhs(w.M, w.nu, w.lam0, 0.0, X, Mo, dX, dM, 0)
+    with pytest.raises(mm.MMVMError) as e:
+        mm.sync()
+    assert e.value.status == -8
+
+
+# ---------------------------------------------------------------------------
+# RK4 stepping
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,M,steps", [(1, 6, 20), (3, 3, 10), (4, 2, 25)])
+def test_step_matches_oracle(env, orc, N, M, steps):
+    w = rand_workload(200 + N, N, M)
+    w.dt = 2e-3
+    x_r, m_r = orc.rk4(M, w.nu, w.lam0, 0.1, w.dt, steps, w.x, w.mom)
+    for prec, tol in ((0, FP64_TOL), (1, MIXED_TOL)):
+        x_g, m_g = gpu_step(env, w, 0.1, steps, prec)
+        lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * (0.1 + steps * w.dt))
+        assert normwise(M, lam_t, m_r, m_g) <= tol
+        assert np.abs(x_g - x_r).max() <= tol * max(1.0, np.abs(x_r).max())
+        assert np.array_equal(m_g[:, 0], w.mom[:, 0])  # circulation bitwise
+
+
+# ---------------------------------------------------------------------------
+# the workloads at full size (sampled outputs the oracle computes one by one)
+# ---------------------------------------------------------------------------
+def test_single_quadrupole_trajectory(env, orc):
+    """Order 10, Re 1000: 40 RK4 steps against the oracle; the full 1000-step
+    run conserves circulation and keeps the first moments at zero."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_quadrupole()
+    x_r, m_r = orc.rk4(w.M, w.nu, w.lam0, 0.0, w.dt, 40, w.x, w.mom)
+    x_g, m_g = gpu_step(env, w, 0.0, 40, 0)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * 40 * w.dt)
+    assert normwise(w.M, lam_t, m_r, m_g) <= FP64_TOL
+    x_g, m_g = gpu_step(env, w, 0.0, w.steps, 0)
+    assert m_g[0, 0] == 1.0
+    assert np.abs(m_g[0, 1:3]).max() < 1e-16
+    assert np.all(x_g == 0.0)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, 1e-9)])
+def test_single_random_order40_sampled_rows(env, orc, prec, tol):
+    """Order 40 (861 coefficients): sampled rows of dM/dt across all shells."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=40, Re=1000.0)
+    t = 0.5
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    ids = wl.multi_indices(40)
+    rows = [wl.index(1, 1), wl.index(3, 2), wl.index(7, 6), wl.index(0, 17), wl.index(12, 13),
+            wl.index(20, 20), wl.index(40, 0), wl.index(17, 23)]
+    d, _ = orc.rhs_rows(40, w.nu, w.lam0, t, w.x, w.mom, [0] * len(rows), rows)
+    lam = math.sqrt(w.lam0[0] ** 2 + 4 * w.nu * t)
+    n = _nk(40, lam)
+    scale = np.abs(dm_g[0] * n).max()
+    err = max(abs(dm_g[0, r] - d[i]) * n[r] for i, r in enumerate(rows)) / scale
+    assert err <= tol, err
+    assert dm_g[0, 0] == 0.0
+    del ids
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_random_multi_64_sampled(env, orc, prec, tol):
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.random_multi()
+    # give the vortices some structure first (the workload starts as Gaussians)
+    rng = np.random.default_rng(33)
+    w.mom[:, 3:] = rng.normal(0, 0.02, (w.N, w.K - 3)) * w.mom[:, :1]
+    t = 0.2
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    js = [0, 17, 63]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, dxr = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)[js]
+    assert normwise(w.M, lam_t, d.reshape(3, w.K), dm_g[js]) <= tol
+    dx_r = dxr.reshape(3, w.K, 2)[:, 0, :]
+    assert np.abs(dx_g[js] - dx_r).max() <= tol * np.abs(dx_r).max()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_two_clusters_4096_sampled(env, orc, prec, tol):
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.two_clusters()
+    rng = np.random.default_rng(44)
+    w.mom[:, 3:] = rng.normal(0, 0.02, (w.N, w.K - 3)) * w.mom[:, :1]
+    t = 0.1
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    js = [3, 4000]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, dxr = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)[js]
+    assert normwise(w.M, lam_t, d.reshape(2, w.K), dm_g[js]) <= tol
+    dx_r = dxr.reshape(2, w.K, 2)[:, 0, :]
+    assert np.abs(dx_g[js] - dx_r).max() <= tol * np.abs(dx_r).max()
+    # invariants that hold at any size
+    G = w.mom[:, 0]
+    assert np.all(dm_g[:, 0] == 0.0)
+    assert abs((G[:, None] * dx_g).sum(0)).max() <= tol * np.abs(G[:, None] * dx_g).sum()
