@@ -1,0 +1,205 @@
+"""Benchmark of the MMVM hot path on one MI355X.
+
+Workload: the single-particle high-order case -- one vortex of order 40 (861
+Hermite moments), seeded random orthonormal coefficients a~_k ~ N(0,1) 0.05
+2^{-ord k/2} on top of a Lamb-Oseen core (lambda0 = 2), three independent
+solves at Re = 1e2, 1e3, 1e4, classic RK4 with dt = 1e-3.  A step is one RK4
+step of all three solves (each on its own stream).  Metric: moment-updates/s
+(one moment-update = one coefficient advanced one RK4 step), for the mixed
+path (value) and the strict FP64 path (reported beside it), each with its
+error against the FP64 oracle on sampled right-hand-side rows.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP64_ALU = 78.6e12  # 256 CUs x 2.4 GHz x 128 FP64 flops/clk
+ORDER = 40
+RES = (1e2, 1e3, 1e4)
+
+
+def stage2_flops(M):
+    """Multiply-adds of the factorised contraction of one vortex (x2 flops)."""
+    GM = max(2 * M, 1)
+    macs = 0
+    for k2 in range(M + 1):
+        for g1 in range(GM + 1):
+            for l2 in range(M + 1):
+                macs += sum(1 for i in range(min(l2, k2) + 1) if g1 + k2 + l2 - 2 * i + 1 <= GM)
+                macs += sum(1 for i in range(min(l2, k2 - 1) + 1) if 1 <= g1 + k2 + l2 - 2 * i - 1 <= GM)
+        macs += 2 * (GM + 1) * sum(M - l1 + 1 for l1 in range(M + 1))
+        for k1 in range(M - k2 + 1):
+            for l1 in range(M + 1):
+                macs += max(0, min(l1, k1 - 1) + 1)
+                macs += sum(1 for i in range(min(l1, k1) + 1) if k1 + l1 - 2 * i + 1 <= GM)
+    return 2 * macs
+
+
+def self_flops(M):
+    GM = max(2 * M, 1)
+    macs = 0
+    for s in range(1, GM + 1):
+        for g2 in range(s + 1):
+            g1 = s - g2
+            macs += sum(1 for m2 in range(g2 & 1, M + 1, 2) for m1 in range(g1 & 1, M - m2 + 1, 2))
+    return 2 * macs
+
+
+def run_solves(mm, torch, works, prec, t0, nsteps, states, streams):
+    for w, (X, Mo), st in zip(works, states, streams):
+        mm.step(w.M, w.nu, w.lam0, t0, w.dt, nsteps, X, Mo, prec, stream=st)
+
+
+def measure(mm, torch, works, prec, steps, warmup):
+    dev = torch.device("cuda:0")
+    streams = [torch.cuda.Stream(device=dev) for _ in works]
+    states = [(torch.tensor(w.x, device=dev), torch.tensor(w.mom, device=dev)) for w in works]
+    dt = works[0].dt
+    run_solves(mm, torch, works, prec, 0.0, warmup, states, streams)
+    for st in streams:
+        mm.sync(st)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record()
+    ends = []
+    t_a = time.perf_counter()
+    run_solves(mm, torch, works, prec, warmup * dt, steps, states, streams)
+    for st in streams:
+        e = torch.cuda.Event(enable_timing=True)
+        st.wait_event(start)
+        e.record(st)
+        ends.append(e)
+    for st in streams:
+        mm.sync(st)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    lat = sorted(start.elapsed_time(e) for e in ends)
+    return t_b - t_a, lat, states
+
+
+def rhs_error(mm, torch, orc, w, x, mom, prec, t, rows):
+    dev = torch.device("cuda:0")
+    X = torch.tensor(x, device=dev)
+    Mo = torch.tensor(mom, device=dev)
+    dX, dM = torch.zeros_like(X), torch.zeros_like(Mo)
+    mm.rhs(w.M, w.nu, w.lam0, t, X, Mo, dX, dM, prec)
+    mm.sync()
+    g = dM.cpu().numpy()[0]
+    ref, _ = orc.rhs_rows(w.M, w.nu, w.lam0, t, x, mom, [0] * len(rows), rows)
+    from paper_1010_2475_amd import workloads as wl
+    n = wl.orthonormal_scale(w.M, math.sqrt(w.lam0[0] ** 2 + 4 * w.nu * t))
+    return max(abs(g[r] - ref[i]) * n[r] for i, r in enumerate(rows)) / np.abs(g * n).max()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the workload's solves are independent and this build "
+              "measures one MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1010_2475_amd import mmvm as mm
+    from paper_1010_2475_amd import workloads as wl
+
+    mm.lib()
+    works = [wl.single_random(M=ORDER, Re=Re) for Re in RES]
+    K = works[0].K
+    res = {}
+    for name, prec in (("mixed", mm.MIXED), ("fp64", mm.FP64)):
+        print("timing %s: %d warmup + %d steps" % (name, args.warmup, args.steps), file=sys.stderr, flush=True)
+        secs, lat, states = measure(mm, torch, works, prec, args.steps, args.warmup)
+        res[name] = {"secs": secs, "lat_ms": lat, "states": states,
+                     "value": len(works) * K * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps}
+
+    # per-kernel durations with HIP events on the launch streams (separate pass)
+    kt_steps = min(args.steps, 200)
+    kernels = {}
+    for name, prec in (("mixed", mm.MIXED), ("fp64", mm.FP64)):
+        mm.timing_enable(True)
+        measure(mm, torch, works, prec, kt_steps, 0)
+        kernels[name] = {k: mm.timing_get(k) for k in ("prep", "self", "stage2")}
+        mm.timing_enable(False)
+    flops = {"prep": 0, "self": self_flops(ORDER), "stage2": stage2_flops(ORDER)}
+    kern = kernels["mixed"]
+    dom = max(("self", "stage2"), key=lambda k: kern[k][0])
+    avg_ms = kern[dom][0] / max(kern[dom][1], 1)
+    achieved = flops[dom] / (avg_ms * 1e-3)
+
+    out = {
+        "metric": "moment-updates/s (mixed path; strict FP64 path beside it) at stated error vs the FP64 oracle",
+        "value": res["mixed"]["value"],
+        "unit": "moment-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["mixed"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single vortex, order 40 (861 moments), seeded random orthonormal "
+                               "coefficients on a Lamb-Oseen core, Re 1e2/1e3/1e4 (3 solves), RK4 dt 1e-3",
+                   "solves": len(works), "order": ORDER, "moments_per_solve": K},
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "dtype": "f64 state, double-double self contraction"},
+        "solve_latency_ms": {"p50": float(np.median(res["mixed"]["lat_ms"])),
+                             "p99": float(np.percentile(res["mixed"]["lat_ms"], 99)),
+                             "steps": args.steps},
+        "kernels_ms_per_launch": {p: {k: (v[0] / v[1] if v[1] else None) for k, v in kernels[p].items()}
+                                  for p in kernels},
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_ALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_ALU, "traffic": None,
+                     "flops_per_launch": flops[dom], "avg_launch_ms": avg_ms},
+    }
+
+    if not args.no_error or not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+    if not args.no_error:
+        rows = [wl.index(1, 1), wl.index(6, 5), wl.index(10, 14), wl.index(20, 20), wl.index(0, 39),
+                wl.index(33, 7)]
+        w = works[1]
+        t_end = (args.warmup + args.steps) * w.dt
+        for name, prec in (("mixed", mm.MIXED), ("fp64", mm.FP64)):
+            X, Mo = res[name]["states"][1]
+            err = rhs_error(mm, torch, oracle, w, X.cpu().numpy(), Mo.cpu().numpy(), prec, t_end, rows)
+            (out if name == "mixed" else out["fp64"])["err_vs_oracle"] = err
+        out["err_note"] = ("normwise error of dM/dt in orthonormal coefficients on %d sampled rows at the "
+                           "final state of the Re=1e3 solve" % len(rows))
+
+    if not args.no_cpu_baseline:
+        # the oracle as it stands, on a bounded sample: 32 right-hand-side rows
+        # spread over all shells of one solve; 4 rows = one moment-update
+        w = works[1]
+        rows = list(range(0, K, max(1, K // 32)))[:32]
+        t0 = time.perf_counter()
+        oracle.rhs_rows(w.M, w.nu, w.lam0, 0.0, w.x, w.mom, [0] * len(rows), rows)
+        dt_cpu = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": len(rows) / (4.0 * dt_cpu), "unit": "moment-updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "%d rows of one order-40 right-hand side (quad-precision oracle), "
+                                         "%.1f s; 4 rows = 1 moment-update" % (len(rows), dt_cpu)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

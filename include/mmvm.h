@@ -131,6 +131,15 @@ mmvm_status mmvm_poll(mmvm_server* srv, uint64_t ticket, double* x_out, double* 
 mmvm_status mmvm_server_drain(mmvm_server* srv);
 mmvm_status mmvm_server_destroy(mmvm_server* srv);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (profiling aid).  While enabled, every kernel launch of the
+ * library is bracketed by HIP events on its stream; mmvm_timing_get waits for
+ * them and returns the summed duration and launch count of one kernel
+ * ("prep", "self", "pair", "stage2").  Enabling clears the totals.
+ * MMVM_ENOTFOUND if the kernel has not run while enabled. */
+mmvm_status mmvm_timing_enable(int32_t on);
+mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches);
+
 /* Human-readable name of a status code (static string). */
 const char* mmvm_status_string(mmvm_status s);
 

@@ -22,6 +22,8 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
+    # FMA contraction stays on, but the double-double routines switch it off
+    "-ffp-contract=fast-honor-pragmas",
     "-Wno-unused-command-line-argument",
 ]
 

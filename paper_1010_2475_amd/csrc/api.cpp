@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -75,7 +77,10 @@ mmvm_status device_tables(int M, const DevTables** out)
     d.kap0 = upload(*o, H.kap0, err);
     d.kap1 = upload(*o, H.kap1, err);
     d.hol = upload(*o, H.hol, err);
-    if (err != hipSuccess) return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+    if (err != hipSuccess) {
+        report_hip_error(err, "table upload");
+        return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+    }
     *out = &o->t;
     g_dev_tables[key] = std::move(o);
     return MMVM_OK;
@@ -127,7 +132,10 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         }
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, need);
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+        if (e != hipSuccess) {
+            report_hip_error(e, "workspace hipMalloc");
+            return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
+        }
         base = (char*)p;
         bytes = need;
         if (hipMemset(base + o_flag, 0, sizeof(int) * 16) != hipSuccess) return MMVM_EDEVICE;
@@ -196,9 +204,16 @@ mmvm_status validate(const mmvm_problem* prob)
 
 bool use_dd(int M, mmvm_precision prec) { return prec == MMVM_FP64 && M > kDDThreshold; }
 
-static mmvm_status hip_status(hipError_t e)
+void report_hip_error(hipError_t e, const char* where)
+{
+    if (e == hipSuccess || std::getenv("MMVM_QUIET")) return;
+    std::fprintf(stderr, "libmmvm: %s failed: %s\n", where, hipGetErrorString(e));
+}
+
+static mmvm_status hip_status(hipError_t e, const char* where)
 {
     if (e == hipSuccess) return MMVM_OK;
+    report_hip_error(e, where);
     return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
 }
 
@@ -209,11 +224,24 @@ mmvm_status run_rhs_core(const DevTables& T, Workspace& W, const double* xin, co
     const bool pair = W.bufs.N > 1;
     const bool f32 = prec == MMVM_MIXED;
     const bool dd = use_dd(T.M, prec);
+    void* tk = timing_begin(st);
     hipError_t e = launch_prep(T, W.bufs, xin, min_, t, nu, pair, f32, st);
-    if (e == hipSuccess) e = launch_self(T, W.bufs, dd, st);
-    if (e == hipSuccess && pair) e = launch_pair(T, W.bufs, f32, 1, st);
-    if (e == hipSuccess) e = launch_stage2(T, W.bufs, A, dd, st);
-    return hip_status(e);
+    timing_end(tk, "prep", st);
+    if (e != hipSuccess) return hip_status(e, "k_prep launch");
+    tk = timing_begin(st);
+    e = launch_self(T, W.bufs, dd, st);
+    timing_end(tk, "self", st);
+    if (e != hipSuccess) return hip_status(e, "k_self launch");
+    if (pair) {
+        tk = timing_begin(st);
+        e = launch_pair(T, W.bufs, f32, 1, st);
+        timing_end(tk, "pair", st);
+        if (e != hipSuccess) return hip_status(e, "k_pair launch");
+    }
+    tk = timing_begin(st);
+    e = launch_stage2(T, W.bufs, A, dd, st);
+    timing_end(tk, "stage2", st);
+    return hip_status(e, "k_stage2 launch");
 }
 
 }  // namespace mmvm

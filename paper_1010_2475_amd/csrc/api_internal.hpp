@@ -33,6 +33,11 @@ struct Workspace {
 };
 
 mmvm_status device_tables(int M, const DevTables** out);
+
+// per-kernel timing (mmvm_timing_enable); no-ops when disabled
+bool timing_on();
+void* timing_begin(hipStream_t st);
+void timing_end(void* tok, const char* name, hipStream_t st);
 Workspace* workspace_for(hipStream_t st);
 mmvm_status validate(const mmvm_problem* prob);
 bool use_dd(int M, mmvm_precision prec);

@@ -373,14 +373,15 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     size_t elem = use_dd ? sizeof(dd) : sizeof(double);
     size_t shmem = elem * ((size_t)T.K + 2 * (size_t)rows * M1 + (size_t)M1 * M1);
     dim3 grid(nslab, B.N);
-    static bool attr_set = false;
-    if (!attr_set) {
-        // the contraction stages up to ~150 KB of LDS at order 40 (double-double)
-        (void)hipFuncSetAttribute((const void*)k_stage2<ArithDD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        (void)hipFuncSetAttribute((const void*)k_stage2<ArithF64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
+    if (shmem > 64 * 1024) {
+        // large orders stage up to ~150 KB of LDS (double-double at order 40)
+        const void* fn = use_dd ? (const void*)k_stage2<ArithDD> : (const void*)k_stage2<ArithF64>;
+        hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (ea != hipSuccess) {
+            (void)hipGetLastError();
+            report_hip_error(ea, "hipFuncSetAttribute(k_stage2 dynamic LDS)");
+            return ea;
+        }
     }
     if (use_dd)
         hipLaunchKernelGGL(k_stage2<ArithDD>, grid, dim3(threads), shmem, st, T, B, A, nslab);

@@ -72,4 +72,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
 constexpr int kMaxPairOrder = 6;
 bool pair_order_supported(int M);
 
+// prints a HIP error with its location to stderr (unless MMVM_QUIET is set)
+void report_hip_error(hipError_t e, const char* where);
+
 }  // namespace mmvm

@@ -1,0 +1,109 @@
+// Optional per-kernel timing with HIP events recorded on the launch stream.
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "api_internal.hpp"
+
+namespace mmvm {
+
+namespace {
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+};
+struct Acc {
+    double ms = 0.0;
+    int64_t n = 0;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, Acc> g_acc;
+
+hipEvent_t get_event()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void collect_locked()
+{
+    for (auto& p : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            Acc& a = g_acc[p.name];
+            a.ms += ms;
+            a.n += 1;
+        }
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+bool timing_on()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_on;
+}
+
+void* timing_begin(hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on) return nullptr;
+    hipEvent_t a = get_event();
+    (void)hipEventRecord(a, st);
+    return (void*)a;
+}
+
+void timing_end(void* tok, const char* name, hipStream_t st)
+{
+    if (!tok) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t b = get_event();
+    (void)hipEventRecord(b, st);
+    g_pending.push_back(Pending{name, (hipEvent_t)tok, b});
+    if (g_pending.size() > 4096) collect_locked();
+}
+
+}  // namespace mmvm
+
+using namespace mmvm;
+
+extern "C" {
+
+mmvm_status mmvm_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    collect_locked();
+    g_on = on != 0;
+    if (on) g_acc.clear();
+    return MMVM_OK;
+}
+
+mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches)
+{
+    if (!kernel || !total_ms || !launches) return MMVM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    collect_locked();
+    auto it = g_acc.find(kernel);
+    if (it == g_acc.end()) {
+        *total_ms = 0.0;
+        *launches = 0;
+        return MMVM_ENOTFOUND;
+    }
+    *total_ms = it->second.ms;
+    *launches = it->second.n;
+    return MMVM_OK;
+}
+}

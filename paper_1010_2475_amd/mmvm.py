@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
 _lib = None
 
 SYMBOLS = ["mmvm_coeffs", "mmvm_rhs", "mmvm_step", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
-           "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_status_string"]
+           "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
+           "mmvm_status_string"]
 
 
 def lib():
@@ -67,6 +68,8 @@ def lib():
     L.mmvm_poll.argtypes = [vp, ctypes.c_uint64, dp, dp, ctypes.POINTER(Stats)]
     L.mmvm_server_drain.argtypes = [vp]
     L.mmvm_server_destroy.argtypes = [vp]
+    L.mmvm_timing_enable.argtypes = [ctypes.c_int32]
+    L.mmvm_timing_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.mmvm_status_string.argtypes = [ctypes.c_int]
     L.mmvm_status_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -137,6 +140,20 @@ def step(M, nu, lambda0, t0, dt, nsteps, x, mom, prec=FP64, stream=None):
 
 def sync(stream=None):
     _check(lib().mmvm_sync(_stream(stream)), "mmvm_sync")
+
+
+def timing_enable(on):
+    _check(lib().mmvm_timing_enable(1 if on else 0), "mmvm_timing_enable")
+
+
+def timing_get(kernel):
+    """(total_ms, launches) of one kernel since timing was enabled."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    rc = lib().mmvm_timing_get(kernel.encode(), ctypes.byref(ms), ctypes.byref(n))
+    if rc not in (OK, -6):
+        _check(rc, "mmvm_timing_get")
+    return ms.value, n.value
 
 
 class Server:

@@ -71,16 +71,36 @@ def gpu_step(env, w, t0, nsteps, prec):
 
 
 def rand_workload(seed, N, M, amp=0.08, spread=1.5):
+    """Random vortices with physically scaled moments: orthonormal coefficients
+    a~_k = Gamma * amp * 2^{-|k|/2} * N(0,1) (finite weighted enstrophy, the
+    regime where the Hermite expansion converges), first moments zero."""
     from paper_1010_2475_amd import workloads as wl
     rng = np.random.default_rng(seed)
     K = wl.K_of(M)
     x = rng.uniform(-spread, spread, (N, 2))
-    mom = rng.normal(0.0, amp, (N, K))
-    mom[:, 0] = rng.uniform(0.4, 1.0, N) * rng.choice([-1, 1], N)
+    lam0 = rng.uniform(0.3, 0.7, N)
+    gam = rng.uniform(0.4, 1.0, N) * rng.choice([-1, 1], N)
+    mom = np.zeros((N, K))
+    shells = np.array([a + b for (a, b) in wl.multi_indices(M)])
+    for j in range(N):
+        at = rng.normal(0.0, 1.0, K) * amp * 2.0 ** (-shells / 2.0) * gam[j]
+        at[0] = gam[j]
+        mom[j] = at / wl.orthonormal_scale(M, lam0[j])
     if M >= 1:
         mom[:, 1:3] = 0.0
-    lam0 = rng.uniform(0.3, 0.7, N)
     return wl.Workload("rand", M, x, mom, lam0, 0.005, 1e-3, 10)
+
+
+def structure(w, seed, amp=0.05):
+    """Adds decaying orthonormal higher moments to a workload that starts as
+    plain Gaussians, as its evolution would."""
+    from paper_1010_2475_amd import workloads as wl
+    rng = np.random.default_rng(seed)
+    shells = np.array([a + b for (a, b) in wl.multi_indices(w.M)])
+    for j in range(w.N):
+        at = rng.normal(0.0, 1.0, w.K) * amp * 2.0 ** (-shells / 2.0) * w.mom[j, 0]
+        at[:3] = 0.0
+        w.mom[j] += at / wl.orthonormal_scale(w.M, w.lam0[j])
 
 
 # ---------------------------------------------------------------------------
@@ -227,8 +247,7 @@ def test_random_multi_64_sampled(env, orc, prec, tol):
     from paper_1010_2475_amd import workloads as wl
     w = wl.random_multi()
     # give the vortices some structure first (the workload starts as Gaussians)
-    rng = np.random.default_rng(33)
-    w.mom[:, 3:] = rng.normal(0, 0.02, (w.N, w.K - 3)) * w.mom[:, :1]
+    structure(w, 33)
     t = 0.2
     dx_g, dm_g = gpu_rhs(env, w, t, prec)
     js = [0, 17, 63]
@@ -245,8 +264,7 @@ def test_random_multi_64_sampled(env, orc, prec, tol):
 def test_two_clusters_4096_sampled(env, orc, prec, tol):
     from paper_1010_2475_amd import workloads as wl
     w = wl.two_clusters()
-    rng = np.random.default_rng(44)
-    w.mom[:, 3:] = rng.normal(0, 0.02, (w.N, w.K - 3)) * w.mom[:, :1]
+    structure(w, 44)
     t = 0.1
     dx_g, dm_g = gpu_rhs(env, w, t, prec)
     js = [3, 4000]
