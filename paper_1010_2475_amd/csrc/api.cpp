@@ -77,6 +77,9 @@ mmvm_status device_tables(int M, const DevTables** out)
     d.kap0 = upload(*o, H.kap0, err);
     d.kap1 = upload(*o, H.kap1, err);
     d.hol = upload(*o, H.hol, err);
+    std::vector<double> rcp(128, 0.0);
+    for (int i = 1; i < 128; ++i) rcp[i] = 1.0 / (double)i;
+    d.rcp = upload(*o, rcp, err);
     if (err != hipSuccess) {
         report_hip_error(err, "table upload");
         return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
@@ -113,13 +116,18 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     size_t o_ys = add(sizeof(double) * (size_t)N_ * K);
     size_t o_accx = add(sizeof(double) * 2 * N_);
     size_t o_accm = add(sizeof(double) * (size_t)N_ * K);
-    size_t o_lam2 = add(sizeof(double) * N_);
-    size_t o_alpha = add(sizeof(double) * (size_t)N_ * K);
-    size_t o_alphaT = add(sizeof(double) * (size_t)N_ * K);
-    size_t o_alphaT32 = add(sizeof(float) * (size_t)N_ * K);
+    size_t o_lam2[2], o_alpha[2], o_alphaT[2], o_alphaT32[2];
+    for (int b = 0; b < 2; ++b) {
+        o_lam2[b] = add(sizeof(double) * N_);
+        o_alpha[b] = add(sizeof(double) * (size_t)N_ * K);
+        o_alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
+        o_alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
+    }
     size_t o_sself = add(sizeof(double) * (size_t)N_ * KG);
     size_t o_sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     size_t o_spair = add(sizeof(double) * (size_t)N_ * KG);
+    size_t o_gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
+    size_t o_done = add(sizeof(unsigned) * (size_t)N_);
     if (need > bytes) {
         // the old buffer may still be used by queued work on this stream
         if (base) {
@@ -138,7 +146,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         }
         base = (char*)p;
         bytes = need;
-        if (hipMemset(base + o_flag, 0, sizeof(int) * 16) != hipSuccess) return MMVM_EDEVICE;
+        if (hipMemset(base, 0, need) != hipSuccess) return MMVM_EDEVICE;  // flag and counters start at 0
         lam0_cache.clear();
     }
     N = N_;
@@ -150,13 +158,17 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.ys = (double*)(b + o_ys);
     bufs.accx = (double*)(b + o_accx);
     bufs.accm = (double*)(b + o_accm);
-    bufs.lam2 = (double*)(b + o_lam2);
-    bufs.alpha = (double*)(b + o_alpha);
-    bufs.alphaT = (double*)(b + o_alphaT);
-    bufs.alphaT32 = (float*)(b + o_alphaT32);
+    for (int q = 0; q < 2; ++q) {
+        bufs.lam2[q] = (double*)(b + o_lam2[q]);
+        bufs.alpha[q] = (double*)(b + o_alpha[q]);
+        bufs.alphaT[q] = (double*)(b + o_alphaT[q]);
+        bufs.alphaT32[q] = (float*)(b + o_alphaT32[q]);
+    }
     bufs.s_self = (double*)(b + o_sself);
     bufs.s_self_lo = need_dd ? (double*)(b + o_sselflo) : nullptr;
     bufs.s_pair = (double*)(b + o_spair);
+    bufs.gpart = (double*)(b + o_gpart);
+    bufs.done = (unsigned*)(b + o_done);
     bufs.flag = (int*)(b + o_flag);
     flag_ptr = bufs.flag;
     lam0_dev = (double*)(b + o_lam0);
@@ -217,24 +229,23 @@ static mmvm_status hip_status(hipError_t e, const char* where)
     return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
 }
 
-// one right-hand side on the stage input (xin, min_) at time t
-mmvm_status run_rhs_core(const DevTables& T, Workspace& W, const double* xin, const double* min_, double t,
-                         double nu, mmvm_precision prec, const StageArgs& A, hipStream_t st)
+// the kernels of one stage whose inputs are in buffer A.cur (prep already ran)
+mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st)
 {
     const bool pair = W.bufs.N > 1;
     const bool f32 = prec == MMVM_MIXED;
     const bool dd = use_dd(T.M, prec);
-    void* tk = timing_begin(st);
-    hipError_t e = launch_prep(T, W.bufs, xin, min_, t, nu, pair, f32, st);
-    timing_end(tk, "prep", st);
-    if (e != hipSuccess) return hip_status(e, "k_prep launch");
-    tk = timing_begin(st);
-    e = launch_self(T, W.bufs, dd, st);
-    timing_end(tk, "self", st);
-    if (e != hipSuccess) return hip_status(e, "k_self launch");
+    hipError_t e;
+    void* tk;
+    if (!stage2_fuses_self(T.M, dd)) {
+        tk = timing_begin(st);
+        e = launch_self(T, W.bufs, A.cur, dd, st);
+        timing_end(tk, "self", st);
+        if (e != hipSuccess) return hip_status(e, "k_self launch");
+    }
     if (pair) {
         tk = timing_begin(st);
-        e = launch_pair(T, W.bufs, f32, 1, st);
+        e = launch_pair(T, W.bufs, A.cur, f32, st);
         timing_end(tk, "pair", st);
         if (e != hipSuccess) return hip_status(e, "k_pair launch");
     }
@@ -242,6 +253,16 @@ mmvm_status run_rhs_core(const DevTables& T, Workspace& W, const double* xin, co
     e = launch_stage2(T, W.bufs, A, dd, st);
     timing_end(tk, "stage2", st);
     return hip_status(e, "k_stage2 launch");
+}
+
+// stage inputs (xin, min_) at time t -> buffer `cur`
+mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
+                     double nu, mmvm_precision prec, hipStream_t st)
+{
+    void* tk = timing_begin(st);
+    hipError_t e = launch_prep(T, W.bufs, cur, xin, min_, t, nu, W.bufs.N > 1, prec == MMVM_MIXED, st);
+    timing_end(tk, "prep", st);
+    return hip_status(e, "k_prep launch");
 }
 
 }  // namespace mmvm
@@ -325,11 +346,14 @@ mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const 
     StageArgs A;
     std::memset(&A, 0, sizeof(A));
     A.mode = MODE_RHS;
+    A.cur = 0;
     A.t_stage = t;
+    A.t_next = t;
     A.nu = prob->nu;
     A.dx = dx;
     A.dmom = dmom;
-    return run_rhs_core(*T, *W, x, mom, t, prob->nu, prec, A, st);
+    if ((s = run_prep(*T, *W, 0, x, mom, t, prob->nu, prec, st)) != MMVM_OK) return s;
+    return run_stage(*T, *W, prec, A, st);
 }
 
 mmvm_status mmvm_step(const mmvm_problem* prob, double t0, double dt, int64_t nsteps, double* x, double* mom,

@@ -41,8 +41,9 @@ void timing_end(void* tok, const char* name, hipStream_t st);
 Workspace* workspace_for(hipStream_t st);
 mmvm_status validate(const mmvm_problem* prob);
 bool use_dd(int M, mmvm_precision prec);
-mmvm_status run_rhs_core(const DevTables& T, Workspace& W, const double* xin, const double* min_, double t,
-                         double nu, mmvm_precision prec, const StageArgs& A, hipStream_t st);
+mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
+                     double nu, mmvm_precision prec, hipStream_t st);
+mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st);
 mmvm_status run_steps(const DevTables& T, Workspace& W, double nu, double t0, double dt, int64_t nsteps,
                       double* x, double* mom, mmvm_precision prec, hipStream_t st);
 

@@ -20,9 +20,13 @@ struct DevTables {
     const double* kap0;    // [P+1][P+1]
     const double* kap1;
     const double* hol;     // [P+1]
+    const double* rcp;     // [128] rcp[i] = 1/i (rcp[0] = 0)
 };
 
-// Stage state and scratch of one solve of N vortices at order M.
+// Stage state and scratch of one solve of N vortices at order M.  The scaled
+// moments, their source-major copies and lambda^2 are double-buffered: a
+// stage reads buffer `cur` and its last kernel writes the next stage's inputs
+// into buffer 1 - cur.
 struct StageBufs {
     int N;
     const double* lam0sq;  // [N] lambda_{j,0}^2
@@ -30,13 +34,15 @@ struct StageBufs {
     double* ys;            // [N][K] stage input moments
     double* accx;          // [N][2] RK4 accumulators
     double* accm;          // [N][K]
-    double* lam2;          // [N] lambda_j(t_s)^2
-    double* alpha;         // [N][K] scaled moments M_k / lambda^{|k|}
-    double* alphaT;        // [K][N] the same, transposed (FP64 pair kernel)
-    float* alphaT32;       // [K][N] FP32 copy (mixed pair kernel)
+    double* lam2[2];       // [N] lambda_j(t_s)^2
+    double* alpha[2];      // [N][K] scaled moments M_k / lambda^{|k|}
+    double* alphaT[2];     // [K][N] the same, source-major (FP64 pair kernel)
+    float* alphaT32[2];    // [K][N] FP32 copy (mixed pair kernel)
     double* s_self;        // [N][KG] self velocity-derivative table (lambda units)
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
+    double* gpart;         // [N][4][K][2] partial contractions of the large-order stage 2 (hi, lo)
+    unsigned* done;        // [N] workgroup counters of the large-order stage 2 (self-resetting)
     int* flag;             // device error flag (bit 0: zero circulation, bit 1: non-finite)
 };
 
@@ -45,8 +51,11 @@ enum StageMode { MODE_RHS = 0, MODE_RK4 = 1 };
 struct StageArgs {
     int mode;
     int stage;         // RK4 stage 0..3
+    int cur;           // buffer holding this stage's inputs
+    int want_pair;     // the next stage runs the pair kernel (write alphaT)
+    int want_f32;      // ... in FP32
     double t_stage;    // time of this stage
-    double t_next;     // time of the next stage input (for lambda)
+    double t_next;     // time of the next stage (lambda of the next inputs)
     double dt;
     double nu;
     // RK4 state (in place) / RHS outputs
@@ -56,14 +65,17 @@ struct StageArgs {
     double* dmom;      // RHS output      [N][K]
 };
 
-// prep: stage input (xs, ys) -> lam2, alpha, alphaT; checks circulation/finiteness
-hipError_t launch_prep(const DevTables& T, const StageBufs& B, const double* xin, const double* min_,
+// prep: stage input (xin, min_) -> lam2[cur], alpha[cur], alphaT[cur]; checks
+// circulation/finiteness; copies the state into (xs, ys) when they differ
+hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
                        double t, double nu, bool need_pair, bool need_f32, hipStream_t st);
-// self velocity-derivative table; dd = use double-double
-hipError_t launch_self(const DevTables& T, const StageBufs& B, bool dd, hipStream_t st);
+// self velocity-derivative table (orders without a fused self term); dd = double-double
+hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st);
 // pair velocity-derivative table (N > 1); f32 = mixed precision
-hipError_t launch_pair(const DevTables& T, const StageBufs& B, bool f32, int lanes_per_pair,
-                       hipStream_t st);
+hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
+// orders whose stage-2 kernel computes the self table itself
+constexpr int kMaxSmallOrder = 10;
+bool stage2_fuses_self(int M, bool dd);
 // stage-2 contraction + drift + RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,
                          hipStream_t st);

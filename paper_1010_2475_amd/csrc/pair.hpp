@@ -10,6 +10,10 @@
 
 namespace mmvm {
 
+// terms of the series e^{-w} sum_k w^k/(P+k)! for w <= P: the tail ratio is at
+// most w/(P+k+1) <= P/(P+k+1), so 56 terms reach double precision for P <= 18
+constexpr int kSeriesTerms = 56;
+
 // ---------------------------------------------------------------------------
 // pair velocity-derivative table.
 //
@@ -34,7 +38,7 @@ template <int M, typename R>
 __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ xs, const double* __restrict__ lam2,
                                               const R* __restrict__ aT, const double* __restrict__ kap0,
                                               const double* __restrict__ kap1, const double* __restrict__ hol,
-                                              double* __restrict__ spair)
+                                              const double* __restrict__ rcp, double* __restrict__ spair)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -68,25 +72,29 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
         const double e1 = exp(-s1 * s1), e2 = exp(-s2 * s2);
         const double E = e1 * e2;
 
-        // g_n = P(n, w) / w^n, n = 1..P
+        // g_n = P(n, w) / w^n, n = 1..P (P the regularised lower incomplete
+        // gamma function), by the downward recurrence g_n = w g_{n+1} + e^{-w}/n!
+        // from g_P:  w <= P: g_P = e^{-w} sum_k w^k/(P+k)!  (fixed-length Horner);
+        //            w >  P: g_P = (1 - e^{-w} sum_{k<P} w^k/k!) / w^P.
         double gsr[P + 1];
         {
-            double ifP = 1.0;
-            for (int f = 2; f <= P; ++f) ifP /= (double)f;
+            double ifP = 1.0;  // 1/P!
+            for (int f = 2; f <= P; ++f) ifP *= rcp[f];
             double gP;
             if (w <= (double)P) {
                 double term = ifP, sum = 0.0;
-                for (int k = 0; k < 400; ++k) {
+#pragma unroll 1
+                for (int k = 0; k < kSeriesTerms; ++k) {
                     sum += term;
-                    term *= w / (double)(P + k + 1);
-                    if (term < 1e-17 * sum) break;
+                    term *= w * rcp[P + k + 1];
                 }
                 gP = E * sum;
             } else {
                 double sm = 0.0, term = 1.0, wp = 1.0;
+#pragma unroll 1
                 for (int k = 0; k < P; ++k) {
                     sm += term;
-                    term *= w / (double)(k + 1);
+                    term *= w * rcp[k + 1];
                     wp *= w;
                 }
                 gP = (1.0 - E * sm) / wp;
@@ -96,7 +104,7 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
             sfor<1, P>([&](auto q) {
                 constexpr int n = P - q;  // P-1 .. 1
                 ifn *= (double)(n + 1);   // 1/n!
-                gsr[n] = w * gsr[n + 1] + E * ifn;
+                gsr[n] = fma(w, gsr[n + 1], E * ifn);
             });
         }
 
@@ -205,16 +213,16 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
 }
 
 template <int M>
-hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, bool f32, hipStream_t st)
+hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
 {
     const int wpb = 4;
     dim3 grid((B.N + wpb - 1) / wpb);
     if (f32)
-        hipLaunchKernelGGL((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2, B.alphaT32, T.kap0,
-                           T.kap1, T.hol, B.s_pair);
+        hipLaunchKernelGGL((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT32[cur], T.kap0,
+                           T.kap1, T.hol, T.rcp, B.s_pair);
     else
-        hipLaunchKernelGGL((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2, B.alphaT, T.kap0,
-                           T.kap1, T.hol, B.s_pair);
+        hipLaunchKernelGGL((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT[cur], T.kap0,
+                           T.kap1, T.hol, T.rcp, B.s_pair);
     return hipGetLastError();
 }
 

@@ -2,5 +2,5 @@
 #include "pair.hpp"
 
 namespace mmvm {
-template hipError_t launch_pair_M<1>(const DevTables&, const StageBufs&, bool, hipStream_t);
+template hipError_t launch_pair_M<1>(const DevTables&, const StageBufs&, int, bool, hipStream_t);
 }

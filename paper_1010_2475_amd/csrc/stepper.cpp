@@ -1,4 +1,6 @@
-// RK4 stepping on the device: nsteps x 4 stages, each one right-hand side.
+// RK4 stepping on the device: nsteps x 4 stages.  The state is read once by
+// the prep kernel; afterwards every stage's last kernel writes the next
+// stage's inputs (double-buffered), so a stage costs its compute kernels only.
 #include <cstring>
 
 #include "api_internal.hpp"
@@ -8,7 +10,7 @@ namespace mmvm {
 mmvm_status run_steps(const DevTables& T, Workspace& W, double nu, double t0, double dt, int64_t nsteps,
                       double* x, double* mom, mmvm_precision prec, hipStream_t st)
 {
-    static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double cst[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
     StageArgs A;
     std::memset(&A, 0, sizeof(A));
     A.mode = MODE_RK4;
@@ -16,16 +18,21 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double nu, double t0, do
     A.nu = nu;
     A.x = x;
     A.mom = mom;
+    A.want_pair = W.bufs.N > 1;
+    A.want_f32 = prec == MMVM_MIXED;
+    int cur = 0;
+    mmvm_status r = run_prep(T, W, cur, x, mom, t0, nu, prec, st);
+    if (r != MMVM_OK) return r;
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int s = 0; s < 4; ++s) {
-            const double ts = t0 + ((double)n + cst[s]) * dt;
             A.stage = s;
-            A.t_stage = ts;
-            const bool first = (n == 0 && s == 0);
-            const double* xin = first ? x : W.bufs.xs;
-            const double* min_ = first ? mom : W.bufs.ys;
-            mmvm_status r = run_rhs_core(T, W, xin, min_, ts, nu, prec, A, st);
+            A.cur = cur;
+            A.t_stage = t0 + ((double)n + cst[s]) * dt;
+            // the next stage's time: c_{s+1}, or the next step's first stage
+            A.t_next = t0 + ((double)n + cst[s + 1]) * dt;
+            r = run_stage(T, W, prec, A, st);
             if (r != MMVM_OK) return r;
+            cur ^= 1;
         }
     }
     return MMVM_OK;
