@@ -99,35 +99,51 @@ void Workspace::release()
     bytes = 0;
 }
 
-mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
+namespace {
+struct Layout {
+    size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], sself, sselflo, spair, gpart,
+        done, total;
+};
+Layout layout_for(int N_, int M_, bool need_dd)
 {
     const int K = (M_ + 1) * (M_ + 2) / 2;
     const int GM = M_ == 0 ? 1 : 2 * M_;
     const int KG = (GM + 1) * (GM + 2) / 2;
+    Layout L{};
     size_t need = 0;
     auto add = [&](size_t n) {
         size_t o = need;
         need += (n + 63) & ~(size_t)63;
         return o;
     };
-    size_t o_flag = add(sizeof(int) * 16);  // first: fixed offset across layouts
-    size_t o_lam0 = add(sizeof(double) * N_);
-    size_t o_xs = add(sizeof(double) * 2 * N_);
-    size_t o_ys = add(sizeof(double) * (size_t)N_ * K);
-    size_t o_accx = add(sizeof(double) * 2 * N_);
-    size_t o_accm = add(sizeof(double) * (size_t)N_ * K);
-    size_t o_lam2[2], o_alpha[2], o_alphaT[2], o_alphaT32[2];
+    L.flag = add(sizeof(int) * 16);  // first: fixed offset across layouts
+    L.lam0 = add(sizeof(double) * N_);
+    L.xs = add(sizeof(double) * 2 * N_);
+    L.ys = add(sizeof(double) * (size_t)N_ * K);
+    L.accx = add(sizeof(double) * 2 * N_);
+    L.accm = add(sizeof(double) * (size_t)N_ * K);
     for (int b = 0; b < 2; ++b) {
-        o_lam2[b] = add(sizeof(double) * N_);
-        o_alpha[b] = add(sizeof(double) * (size_t)N_ * K);
-        o_alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
-        o_alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
+        L.lam2[b] = add(sizeof(double) * N_);
+        L.alpha[b] = add(sizeof(double) * (size_t)N_ * K);
+        L.alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
+        L.alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
     }
-    size_t o_sself = add(sizeof(double) * (size_t)N_ * KG);
-    size_t o_sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
-    size_t o_spair = add(sizeof(double) * (size_t)N_ * KG);
-    size_t o_gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
-    size_t o_done = add(sizeof(unsigned) * (size_t)N_);
+    L.sself = add(sizeof(double) * (size_t)N_ * KG);
+    L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
+    L.spair = add(sizeof(double) * (size_t)N_ * KG);
+    L.gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
+    L.done = add(sizeof(unsigned) * (size_t)N_);
+    L.total = need;
+    return L;
+}
+}  // namespace
+
+size_t Workspace::bytes_for(int N_, int M_, bool need_dd) { return layout_for(N_, M_, need_dd).total; }
+
+mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
+{
+    const Layout L = layout_for(N_, M_, need_dd);
+    const size_t need = L.total;
     if (need > bytes) {
         // the old buffer may still be used by queued work on this stream
         if (base) {
@@ -153,25 +169,25 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     M = M_;
     char* b = base;
     bufs.N = N_;
-    bufs.lam0sq = (const double*)(b + o_lam0);
-    bufs.xs = (double*)(b + o_xs);
-    bufs.ys = (double*)(b + o_ys);
-    bufs.accx = (double*)(b + o_accx);
-    bufs.accm = (double*)(b + o_accm);
+    bufs.lam0sq = (const double*)(b + L.lam0);
+    bufs.xs = (double*)(b + L.xs);
+    bufs.ys = (double*)(b + L.ys);
+    bufs.accx = (double*)(b + L.accx);
+    bufs.accm = (double*)(b + L.accm);
     for (int q = 0; q < 2; ++q) {
-        bufs.lam2[q] = (double*)(b + o_lam2[q]);
-        bufs.alpha[q] = (double*)(b + o_alpha[q]);
-        bufs.alphaT[q] = (double*)(b + o_alphaT[q]);
-        bufs.alphaT32[q] = (float*)(b + o_alphaT32[q]);
+        bufs.lam2[q] = (double*)(b + L.lam2[q]);
+        bufs.alpha[q] = (double*)(b + L.alpha[q]);
+        bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
+        bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
     }
-    bufs.s_self = (double*)(b + o_sself);
-    bufs.s_self_lo = need_dd ? (double*)(b + o_sselflo) : nullptr;
-    bufs.s_pair = (double*)(b + o_spair);
-    bufs.gpart = (double*)(b + o_gpart);
-    bufs.done = (unsigned*)(b + o_done);
-    bufs.flag = (int*)(b + o_flag);
+    bufs.s_self = (double*)(b + L.sself);
+    bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
+    bufs.s_pair = (double*)(b + L.spair);
+    bufs.gpart = (double*)(b + L.gpart);
+    bufs.done = (unsigned*)(b + L.done);
+    bufs.flag = (int*)(b + L.flag);
     flag_ptr = bufs.flag;
-    lam0_dev = (double*)(b + o_lam0);
+    lam0_dev = (double*)(b + L.lam0);
     return MMVM_OK;
 }
 

@@ -27,6 +27,7 @@ struct Workspace {
     int latched = 0;
 
     mmvm_status ensure(int N, int M, bool need_dd, hipStream_t st);
+    static size_t bytes_for(int N, int M, bool need_dd);
     mmvm_status set_lambda0(const double* lambda0, int N, hipStream_t st);
     void release();
     ~Workspace() { release(); }

@@ -1,0 +1,143 @@
+"""GPU tests of the solve server (mmvm_server_*): results are identical alone
+and in the mix, admission respects the HBM budget, errors are reported at
+submit or poll."""
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1010_2475_amd import mmvm
+    mmvm.lib()
+    torch.cuda.init()
+    return mmvm
+
+
+def _requests():
+    from paper_1010_2475_amd import workloads as wl
+    reqs = [wl.single_quadrupole(M=12, delta=0.15, Re=800.0, steps=120),
+            wl.random_multi(N=40, M=4, Re=300.0, seed=11, steps=90),
+            wl.single_random(M=30, Re=2000.0, steps=60),
+            wl.random_multi(N=150, M=3, Re=1000.0, seed=12, steps=50),
+            wl.random_multi(N=20, M=6, Re=500.0, seed=13, steps=80)]
+    return reqs
+
+
+def _solve_alone(mm, w, prec):
+    srv = mm.Server(1 << 30, 4)
+    tk = srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, prec)
+    srv.drain()
+    out = srv.poll(tk, w.N, w.M)
+    srv.close()
+    assert out is not None
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_same_alone_and_in_the_mix(mm, prec):
+    reqs = _requests()
+    alone = [_solve_alone(mm, w, prec) for w in reqs]
+    srv = mm.Server(1 << 30, 3)  # fewer slots than requests: some queue
+    tickets = []
+    for i, w in enumerate(reqs):
+        tickets.append(srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, prec))
+        time.sleep(0.002 * i)  # staggered arrivals while others run
+    srv.drain()
+    for w, tk, (xa, ma, _) in zip(reqs, tickets, alone):
+        x, m, st = srv.poll(tk, w.N, w.M)
+        assert np.array_equal(x, xa) and np.array_equal(m, ma)
+        assert st["steps"] == w.steps
+        assert st["t_arrive"] <= st["t_admit"] <= st["t_start"] <= st["t_done"]
+    srv.close()
+
+
+def test_server_matches_direct_stepping(mm):
+    import torch
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.random_multi(N=30, M=4, Re=400.0, seed=21, steps=70)
+    x_s, m_s, _ = _solve_alone(mm, w, 0)
+    X = torch.tensor(w.x, device="cuda:0")
+    Mo = torch.tensor(w.mom, device="cuda:0")
+    mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, X, Mo, 0)
+    mm.sync()
+    m_d = Mo.cpu().numpy()
+    assert np.abs(m_s - m_d).max() <= 1e-13 * np.abs(m_d).max()
+    assert np.abs(x_s - X.cpu().numpy()).max() <= 1e-13
+
+
+def test_admission_by_budget_and_slots(mm):
+    from paper_1010_2475_amd import workloads as wl
+    reqs = [wl.random_multi(N=64, M=6, Re=500.0, seed=30 + i, steps=40) for i in range(6)]
+    # budget for about two of them at a time
+    one = 8 * 64 * (2 + 28)
+    from paper_1010_2475_amd.mmvm import lib
+    srv = mm.Server(600_000, 8)
+    tks = [srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, 1) for w in reqs]
+    srv.drain()
+    stats = [srv.poll(tk, w.N, w.M)[2] for tk, w in zip(tks, reqs)]
+    # with room for at most two, the later requests were admitted only after earlier ones left
+    admits = sorted(s["t_admit"] for s in stats)
+    dones = sorted(s["t_done"] for s in stats)
+    assert admits[2] >= dones[0]
+    srv.close()
+    del one, lib
+
+
+def test_over_budget_and_bad_inputs_rejected(mm):
+    from paper_1010_2475_amd import workloads as wl
+    srv = mm.Server(10_000, 2)
+    w = wl.random_multi(N=200, M=6, steps=10)
+    with pytest.raises(mm.MMVMError) as e:
+        srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, 1)
+    assert e.value.status == -7
+    srv.close()
+    srv = mm.Server(1 << 28, 2)
+    w = wl.random_multi(N=5, M=2, steps=10)
+    w.mom[2, 0] = 0.0
+    with pytest.raises(mm.MMVMError) as e:
+        srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, 1)
+    assert e.value.status == -4
+    w.mom[2, 0] = 1.0
+    w.mom[3, 4] = float("inf")
+    with pytest.raises(mm.MMVMError) as e:
+        srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, 1)
+    assert e.value.status == -8
+    with pytest.raises(mm.MMVMError) as e:
+        srv.poll(12345, 5, 2)
+    assert e.value.status == -6
+    srv.close()
+
+
+def test_concurrent_submitters(mm):
+    from paper_1010_2475_amd import workloads as wl
+    srv = mm.Server(1 << 30, 6)
+    reqs = [wl.random_multi(N=16 + 4 * i, M=2 + (i % 3), Re=700.0, seed=50 + i, steps=30) for i in range(12)]
+    tickets = [None] * len(reqs)
+
+    def go(i):
+        w = reqs[i]
+        tickets[i] = srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, 1)
+
+    ths = [threading.Thread(target=go, args=(i,)) for i in range(len(reqs))]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    srv.drain()
+    for tk, w in zip(tickets, reqs):
+        x, m, st = srv.poll(tk, w.N, w.M)
+        assert np.all(np.isfinite(m)) and st["steps"] == w.steps
+        assert np.array_equal(m[:, 0], w.mom[:, 0])
+    srv.close()
