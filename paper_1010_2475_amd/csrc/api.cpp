@@ -72,6 +72,34 @@ mmvm_status device_tables(int M, const DevTables** out)
     d.f0_lo = upload(*o, H.f0_lo, err);
     d.f1_hi = upload(*o, H.f1_hi, err);
     d.f1_lo = upload(*o, H.f1_lo, err);
+    d.binom = upload(*o, H.binom, err);
+    d.fd0 = upload(*o, H.fd0, err);
+    d.fd1 = upload(*o, H.fd1, err);
+    {
+        // zero-padded operands of the matrix-core stage 2 (see S2Shape)
+        std::vector<double> wpad, cpad;
+        if (stage2_uses_mfma(M, false)) {
+            const S2Shape sh(M, 0);
+            const int M1 = M + 1, KA = sh.KA, LP = sh.LP;
+            wpad.assign((size_t)M1 * 2 * KA * LP, 0.0);
+            for (int k2 = 0; k2 <= M; ++k2)
+                for (int pass = 0; pass < 2; ++pass) {
+                    const std::vector<double>& F = pass == 0 ? H.f0_hi : H.f1_hi;
+                    const int off2 = pass == 0 ? 1 : -1, imaxk = pass == 0 ? k2 : k2 - 1;
+                    double* w = wpad.data() + ((size_t)k2 * 2 + pass) * KA * LP;
+                    for (int l2 = 0; l2 <= M; ++l2)
+                        for (int i = 0; i <= l2 && i <= imaxk; ++i) {
+                            const int g2 = k2 + l2 + off2 - 2 * i;
+                            if (g2 >= 0 && g2 < KA) w[(size_t)g2 * LP + l2] = F[((size_t)k2 * M1 + l2) * M1 + i];
+                        }
+                }
+            cpad.assign((size_t)LP * LP, 0.0);
+            for (int l = 0; l <= M; ++l)
+                for (int i = 0; i <= l; ++i) cpad[(size_t)l * LP + i] = H.binom[(size_t)l * M1 + i];
+        }
+        d.wpad = upload(*o, wpad, err);
+        d.cpad = upload(*o, cpad, err);
+    }
     d.c1_hi = upload(*o, H.c1_hi, err);
     d.c1_lo = upload(*o, H.c1_lo, err);
     d.kap0 = upload(*o, H.kap0, err);
@@ -101,8 +129,8 @@ void Workspace::release()
 
 namespace {
 struct Layout {
-    size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], sself, sselflo, spair, gpart,
-        done, total;
+    size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], sself, sselflo, spair, spad,
+        gpart, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd)
 {
@@ -131,8 +159,8 @@ Layout layout_for(int N_, int M_, bool need_dd)
     L.sself = add(sizeof(double) * (size_t)N_ * KG);
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
+    L.spad = add(stage2_uses_mfma(M_, false) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     L.gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
-    L.done = add(sizeof(unsigned) * (size_t)N_);
     L.total = need;
     return L;
 }
@@ -162,7 +190,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         }
         base = (char*)p;
         bytes = need;
-        if (hipMemset(base, 0, need) != hipSuccess) return MMVM_EDEVICE;  // flag and counters start at 0
+        if (hipMemset(base, 0, need) != hipSuccess) return MMVM_EDEVICE;  // the error flag starts at 0
         lam0_cache.clear();
     }
     N = N_;
@@ -183,8 +211,8 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.s_self = (double*)(b + L.sself);
     bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
     bufs.s_pair = (double*)(b + L.spair);
+    bufs.s_pad = (double*)(b + L.spad);
     bufs.gpart = (double*)(b + L.gpart);
-    bufs.done = (unsigned*)(b + L.done);
     bufs.flag = (int*)(b + L.flag);
     flag_ptr = bufs.flag;
     lam0_dev = (double*)(b + L.lam0);
@@ -268,7 +296,12 @@ mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, con
     tk = timing_begin(st);
     e = launch_stage2(T, W.bufs, A, dd, st);
     timing_end(tk, "stage2", st);
-    return hip_status(e, "k_stage2 launch");
+    if (e != hipSuccess) return hip_status(e, "k_stage2 launch");
+    if (!stage2_needs_emit(T.M, dd)) return MMVM_OK;
+    tk = timing_begin(st);
+    e = launch_emit(T, W.bufs, A, dd, st);
+    timing_end(tk, "emit", st);
+    return hip_status(e, "k_emit launch");
 }
 
 // stage inputs (xin, min_) at time t -> buffer `cur`

@@ -1,19 +1,21 @@
 // HIP kernels (gfx950) of the MMVM hot path.
 //
-// Per right-hand side (one RK4 stage) the path runs four kernels:
+// Per right-hand side (one RK4 stage) the path runs these kernels:
 //   k_prep    stage input -> lambda_j(t)^2, scaled moments alpha = M_k / lambda^{|k|}
 //             (row-major and source-major copies), circulation/finiteness checks
 //   k_self    self velocity-derivative table  S_self[g] = sum_m alpha_m Psi0(m + g)
 //   k_pair    pair velocity-derivative table  S_pair[g] = sum_{j'} sum_m ... Psi(m + g; s_jj')
 //             (one wavefront per target, lanes over sources, wavefront-shuffle reduction)
-//   k_stage2  the factorised contraction of eq:FinalSingleI/II (self + pair share it),
-//             the drift term, the centre velocity, and the RK4 bookkeeping
+//   k_stage2  the factorised contraction of eq:FinalSingleI/II (self + pair share it);
+//             at small orders also the drift term, the centre velocity and the RK4
+//             bookkeeping, which at large orders a fifth kernel (k_emit) does
 // All quantities are in "lambda units" of the target vortex: with
 // alpha_l = M_l lambda^{-|l|} and S in units lambda^{|g|}, eq:moment_evolutionFinish
 // becomes dM_k/dt = lambda^{|k|-2} G_k(alpha, S) with lambda-free tables.
 #include <type_traits>
 #include <utility>
 
+#include "../../include/mmvm.h"
 #include "dd.hpp"
 #include "kernels.hpp"
 #include "util.hpp"
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(256) void k_prep(int N, int K, const double* __rest
                                               double t, double nu, double* __restrict__ xs, double* __restrict__ ys,
                                               double* __restrict__ lam2, double* __restrict__ alpha,
                                               double* __restrict__ alphaT, float* __restrict__ alphaT32,
-                                              int* __restrict__ flag, unsigned* __restrict__ done, int copy_state)
+                                              int* __restrict__ flag, int copy_state)
 {
     const long total = (long)N * K;
     for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -51,7 +53,6 @@ __global__ __launch_bounds__(256) void k_prep(int N, int K, const double* __rest
         if (!isfinite(mk)) atomicOr(flag, 2);
         if (k == 0) {
             lam2[j] = l2;
-            if (done) done[j] = 0u;
             double x0 = xin[2 * j], x1 = xin[2 * j + 1];
             xs[2 * j] = x0;
             xs[2 * j + 1] = x1;
@@ -70,7 +71,7 @@ hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const do
     bool copy = (min_ != B.ys);
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
                        B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
-                       need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, B.done, copy ? 1 : 0);
+                       need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -129,6 +130,8 @@ __device__ __forceinline__ void emit_position(const StageBufs& B, const StageArg
 // (the target's own Gaussian convolved with itself: Lambda^2 = 2 lambda^2).
 // Psi0 is nonzero only for even-even arguments.
 // ---------------------------------------------------------------------------
+hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipStream_t st);
+
 template <bool DD>
 __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int KG, int T0N,
                                               const double* __restrict__ alpha, const double* __restrict__ t0h,
@@ -193,6 +196,7 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
 
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st)
 {
+    if (stage2_uses_mfma(T.M, dd)) return launch_self_pad(T, B, cur, st);
     const int threads = 256;
     dim3 grid((4 * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
@@ -294,12 +298,16 @@ __device__ void centre_velocity(const double* al, const double* sp, int K, doubl
     xd2 = p2 / (gam * lam);
 }
 
-template <class A, bool FSLICE>
-__global__ __launch_bounds__(512) void k_stage2(DevTables T, StageBufs B, StageArgs S)
+// Large orders, double-double (the FP64 path above the double-double
+// threshold).  blockIdx.x = (k2, pass, par): pass 0 = Y half (f0 on the second
+// axis, f1 on the first, minus sign), pass 1 = X half; par = parity of the rows
+// g1 this workgroup owns (step C of (k1, l1) reads rows of parity k1+l1+1 only).
+// Each workgroup writes its partial sum over l1 for every k1 of its k2; the
+// emit kernel adds the four partials.
+template <bool FSLICE>
+__global__ __launch_bounds__(512) void k_stage2_dd(DevTables T, StageBufs B, StageArgs S)
 {
-    // blockIdx.x = (k2, pass, par): pass 0 = Y half (f0 on the second axis,
-    // f1 on the first, minus sign), pass 1 = X half; par = parity of the rows g1
-    // this workgroup owns (step C of (k1, l1) reads rows of parity k1+l1+1 only).
+    typedef ArithDD A;
     typedef typename A::T R;
     const int M = T.M, K = T.K, GM = T.GM, KG = T.KG, M1 = M + 1;
     const int N = B.N;
@@ -317,8 +325,6 @@ __global__ __launch_bounds__(512) void k_stage2(DevTables T, StageBufs B, StageA
     R* R2 = R1 + KG;
     R* sG = R2 + KG;
     R* sF = sG + M1 * M1;
-    __shared__ double red[16];
-    __shared__ int is_last;
 
     const double* al = B.alpha[S.cur] + (long)j * K;
     for (int l = tid; l < K; l += nt) {
@@ -326,10 +332,10 @@ __global__ __launch_bounds__(512) void k_stage2(DevTables T, StageBufs B, StageA
         sA[l] = A::mk((s & 1) ? -al[l] : al[l]);
     }
     const double* ssh = B.s_self + (long)j * KG;
-    const double* ssl = B.s_self_lo ? B.s_self_lo + (long)j * KG : nullptr;
+    const double* ssl = B.s_self_lo + (long)j * KG;
     const double* sp = N > 1 ? B.s_pair + (long)j * KG : nullptr;
     for (int g = tid; g < KG; g += nt) {
-        R v = ssl ? A::ld(ssh, ssl, g) : A::mk(ssh[g]);
+        R v = A::ld(ssh, ssl, g);
         if (sp) v = A::add(v, A::mk(sp[g]));
         R1[g] = v;
     }
@@ -417,16 +423,352 @@ __global__ __launch_bounds__(512) void k_stage2(DevTables T, StageBufs B, StageA
         const int k = ctri(k1, k2);
         A::st(gp + 2 * k, g);
     }
-    // the last of the 4 (M+1) workgroups of this vortex finishes the stage
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned total = 4u * (unsigned)M1;
-        is_last = atomicAdd(B.done + j, 1u) == total - 1u;
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// A strided LDS matrix: element (i, j) at p[i * rs + j * cs].
+struct View {
+    const double* p;
+    int rs, cs;
+};
+
+// One 16x16 output tile over the k-steps [s0, s1) (s1 - s0 <= KS).  Lane l
+// supplies A[row0 + l%16][4s + l/16] and B[4s + l/16][col0 + l%16]; it receives
+// D[row0 + l/16 + 4q][col0 + l%16] in component q.  All operands are loaded
+// first, then two accumulator chains alternate k-steps.
+template <int KS>
+__device__ __forceinline__ dbl4 mfma_tile(int lane, int row0, int col0, int s0, int s1, const View& A, const View& B)
+{
+    const int lk = lane >> 4;
+    const double* pa = A.p + (row0 + (lane & 15)) * A.rs + (4 * s0 + lk) * A.cs;
+    const double* pb = B.p + (4 * s0 + lk) * B.rs + (col0 + (lane & 15)) * B.cs;
+    const int sa = 4 * A.cs, sb = 4 * B.rs;
+    double a[KS], b[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        if (s0 + q < s1) {
+            a[q] = pa[q * sa];
+            b[q] = pb[q * sb];
+        } else {
+            a[q] = 0.0;
+            b[q] = 0.0;
+        }
+    }
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        if (s0 + q < s1) {
+            if (q & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc1, 0, 0, 0);
+            else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc0, 0, 0, 0);
+        }
+    }
+    return acc0 + acc1;
+}
+
+// largest order of the matrix-core stage 2 and the per-wavefront bounds it implies
+constexpr int kS2TilesPerWave = 2;                         // output tiles of (B) held per wavefront
+constexpr int kS2KA = ((2 * kS2MaxOrder) >> 2) + 1;        // k-steps of (A)
+constexpr int kS2KB = kS2MaxOrder / 4 + 1;                 // k-steps of (B) and (C)
+static_assert(((kS2MaxOrder + 16) / 16) * ((kS2MaxOrder + 16) / 16) <= kS2TilesPerWave * kS2Waves, "tiles");
+static_assert(kS2MaxOrder < 64, "one lane per k1 in the last step");
+static_assert(MMVM_MAX_ORDER <= kS2MaxOrder, "order");
+
+__host__ __device__ inline int s2m_lds_doubles(int M)
+{
+    const S2Shape a(M, 0), b(M, 1);
+    return a.total > b.total ? a.total : b.total;
+}
+
+bool stage2_uses_mfma(int M, bool dd) { return !dd && M > kMaxSmallOrder && M <= kS2MaxOrder; }
+
+// ---------------------------------------------------------------------------
+// Large orders, FP64, on the matrix cores.  Same workgroup split as the
+// double-double kernel; the three steps become products of zero-padded
+// operands staged in LDS, computed with v_mfma_f64_16x16x4f64 (per wavefront
+// D[16x16] += A[16x4] B[4x16]):
+//   (A)  Y[r][l2]  = sum_{g2} S[g1(r)][g2] W[g2][l2],  W[g2][l2] = F[k2][l2][i]
+//        at g2 = k2 + l2 - 2i +- 1 (the factor slice of this k2);
+//   (B)  T[r][l1]  = sum_{l2} Y[r][l2] (-1)^{|l|} alpha[l1, l2]  (l1 + l2 <= M);
+//   (C)  with F'[k1][l1][i] = C(l1, i) F'[k1][i][i]:
+//        U[d][i]   = sum_{l1} T[d + l1][l1] C(l1, i),
+//        G[k1]     = -+ sum_i F'[k1][i][i] U[k1 - 2i -+ 1][i].
+// Rows r index g1 = par + 2r (the rows of this workgroup's parity).  The self
+// kernel writes S in exactly this padded row layout and W and C come padded
+// from the tables, so staging them is a plain copy.  Every output tile runs
+// only over the k-steps where its band of W, the triangle of alpha or the
+// triangle of C is nonzero.  T is stored by (g1, l1) with zero rows for the
+// other parity and kS2TPad zero rows on either side, so that the sheared
+// operand of (C) is the strided view (d, l1) -> T[d + l1][l1].
+// One vortex per workgroup row of the grid (no pair table).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBufs B, StageArgs S)
+{
+    const int M = T.M, K = T.K, GM = T.GM, M1 = M + 1;
+    const int j = blockIdx.y;
+    const int k2 = blockIdx.x >> 2, pass = (blockIdx.x >> 1) & 1, par = blockIdx.x & 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile loops branch on scalars
+    const S2Shape sh(M, par);
+    const int nrp = sh.nrp, LP = sh.LP, KA = sh.KA;
+    const int nk1 = M - k2 + 1;
+    const int dlo = k2 - M + 1;           // step C: d = g1 - l1 in [dlo, dlo + nd)
+    const int nd = 2 * (M - k2) + 1;
+    const int ni = M - k2 + 1;
+    const int off2 = pass == 0 ? 1 : -1;
+    const int imaxk = pass == 0 ? k2 : k2 - 1;
+
+    extern __shared__ double smem[];
+    double* sS = smem + sh.r1;            // S rows [RP][LDS]              (A)
+    double* sW = sS + sh.RP * sh.LDS;     // W [KA][LP]                    (A)
+    double* sT = smem + sh.r1;            // T [NTR][LDT]                  (B -> C)
+    double* sY = smem + sh.y;             // Y [RP][LDY]                   (A -> B)
+    double* sA2 = smem + sh.a2;           // signed alpha [LP][LP] (l2, l1) (B)
+    double* sU = smem + sh.y;             // U [nd][ni], over Y and alpha  (C -> last step)
+    double* sC = smem + sh.cb;            // C(l, i) [LP][LP]              (C); then partial sums
+    double* sG = smem + sh.gd;            // F'[k1][i][i] [M1][M1]         (last step)
+
+    // --- operands: contiguous copies (all loads of a thread issued first)
+    // plus the signed alpha triangle, zero-padded
+    constexpr int kS2Rows = 16 * ((kS2MaxOrder + 16) / 16);
+    constexpr int kSSlots = (kS2Rows * (4 * kS2KA + 1) / 2 + kS2Threads - 1) / kS2Threads;  // double2 of S
+    constexpr int kWSlots = (4 * kS2KA * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;         // double2 of W
+    constexpr int kCSlots = (kS2Rows * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;           // double2 of C
+    constexpr int kDSlots = ((kS2MaxOrder + 1) * (kS2MaxOrder + 1) + kS2Threads - 1) / kS2Threads;
+    constexpr int kASlots = kS2Rows / kS2Waves;                                             // rows of alpha
+    const double2* gS = reinterpret_cast<const double2*>(B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS);
+    const double2* gW = reinterpret_cast<const double2*>(T.wpad + ((long)k2 * 2 + pass) * KA * LP);
+    const double2* gC = reinterpret_cast<const double2*>(T.cpad);
+    const double* gD = pass == 0 ? T.fd1 : T.fd0;
+    const double* al = B.alpha[S.cur] + (long)j * K;
+    const int nS2 = sh.RP * sh.LDS / 2, nW2 = KA * LP / 2, nC2 = LP * LP / 2, nD = M1 * M1;
+    double2 vS[kSSlots], vW[kWSlots], vC[kCSlots];
+    double vD[kDSlots], vA[kASlots];
+#pragma unroll
+    for (int q = 0; q < kSSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        vS[q] = gS[e < nS2 ? e : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kWSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        vW[q] = gW[e < nW2 ? e : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kCSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        vC[q] = gC[e < nC2 ? e : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kDSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        vD[q] = gD[e < nD ? e : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kASlots; ++q) {  // row l2 = wave + 8q, column l1 = lane
+        const int l2 = wave + kS2Waves * q;
+        vA[q] = al[lane + l2 <= M ? ctri(lane, l2) : 0];
+    }
+    double2* dS = reinterpret_cast<double2*>(sS);
+    double2* dW = reinterpret_cast<double2*>(sW);
+    double2* dC = reinterpret_cast<double2*>(sC);
+#pragma unroll
+    for (int q = 0; q < kSSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        if (e < nS2) dS[e] = vS[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kWSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        if (e < nW2) dW[e] = vW[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kCSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        if (e < nC2) dC[e] = vC[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kDSlots; ++q) {
+        const int e = tid + kS2Threads * q;
+        if (e < nD) sG[e] = vD[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kASlots; ++q) {
+        const int l2 = wave + kS2Waves * q;
+        if (l2 < LP && lane < LP) sA2[l2 * LP + lane] = lane + l2 <= M ? (((lane + l2) & 1) ? -vA[q] : vA[q]) : 0.0;
     }
     __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+
+    const int tr = sh.RP >> 4, tc = LP >> 4;
+    // (A)
+    {
+        const View va = {sS, sh.LDS, 1}, vb = {sW, LP, 1};
+        for (int t = wave; t < tr * tc; t += kS2Waves) {
+            const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
+            // W[.][l2] is nonzero for g2 in [lo(l2), k2 + l2 + off2], lo = 1 + |l2 - k2| (pass 0),
+            // |l2 - k2 + 1| (pass 1); row r0 ends at g2 = GM - par - 2 r0
+            const int lhi = c0 + 15 < M ? c0 + 15 : M;
+            const int dist = imaxk < c0 ? c0 - imaxk : (imaxk > lhi ? imaxk - lhi : 0);
+            const int glo = (pass == 0 ? 1 : 0) + dist;
+            int ghi = k2 + off2 + lhi;
+            if (ghi > GM - par - 2 * r0) ghi = GM - par - 2 * r0;
+            const int s0 = glo >> 2, s1 = (c0 <= M && glo <= ghi) ? (ghi >> 2) + 1 : s0;
+            const dbl4 d = mfma_tile<kS2KA>(lane, r0, c0, s0, s1, va, vb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sY[(r0 + (lane >> 4) + 4 * q) * sh.LDY + c0 + (lane & 15)] = d[q];
+        }
+    }
+    __syncthreads();
+    // (B): the results stay in registers until every wavefront has read Y and
+    // the T area (over the operands of A) is cleared
+    {
+        double2* dT = reinterpret_cast<double2*>(sT);
+        const double2 z2 = {0.0, 0.0};
+        for (int e = tid; e < sh.NTR * sh.LDT / 2; e += kS2Threads) dT[e] = z2;
+        if (tid == 0 && (sh.NTR * sh.LDT) & 1) sT[sh.NTR * sh.LDT - 1] = 0.0;
+        const View va = {sY, sh.LDY, 1}, vb = {sA2, LP, 1};
+        dbl4 dt[kS2TilesPerWave];
+#pragma unroll
+        for (int q = 0; q < kS2TilesPerWave; ++q) {
+            const int t = wave + q * kS2Waves;
+            if (t < tr * tc) {
+                const int c0 = (t % tc) * 16;
+                const int s1 = c0 <= M ? (M - c0) / 4 + 1 : 0;
+                dt[q] = mfma_tile<kS2KB>(lane, (t / tc) * 16, c0, 0, s1, va, vb);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kS2TilesPerWave; ++q) {
+            const int t = wave + q * kS2Waves;
+            if (t < tr * tc) {
+                const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = r0 + (lane >> 4) + 4 * u, l1 = c0 + (lane & 15);
+                    if (r < nrp) sT[(par + 2 * r + kS2TPad) * sh.LDT + l1] = dt[q][u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // (C) U = T(sheared) x C
+    {
+        const int td = (nd + 15) >> 4, ti = (ni + 15) >> 4;
+        const View va = {sT + (dlo + kS2TPad) * sh.LDT, sh.LDT, sh.LDT + 1}, vb = {sC, LP, 1};
+        for (int t = wave; t < td * ti; t += kS2Waves) {
+            const int r0 = (t / ti) * 16, c0 = (t % ti) * 16;
+            // l1 >= i >= c0 and 0 <= d + l1 <= GM
+            int llo = -(dlo + r0 + 15);
+            if (llo < c0) llo = c0;
+            int lhi = GM - (dlo + r0);
+            if (lhi > M) lhi = M;
+            const int s0 = llo >> 2, s1 = llo <= lhi ? (lhi >> 2) + 1 : s0;
+            const dbl4 d = mfma_tile<kS2KB>(lane, r0, c0, s0, s1, va, vb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int di = r0 + (lane >> 4) + 4 * q, i = c0 + (lane & 15);
+                if (di < nd && i < ni) sU[di * ni + i] = d[q];
+            }
+        }
+    }
+    __syncthreads();
+    // G[k1] = -+ sum_i F'[k1][i][i] U[k1 - 2i -+ 1][i]: lane = k1, wavefront w takes i = w mod 8
+    {
+        const int k1 = lane;
+        double v = 0.0;
+        if (k1 < nk1) {
+            const int imax = pass == 0 ? k1 - 1 : k1;
+            for (int i = wave; i <= imax; i += kS2Waves) {
+                const int d = pass == 0 ? k1 - 2 * i - 1 : k1 - 2 * i + 1;
+                v = fma(sG[k1 * M1 + i], sU[(d - dlo) * ni + i], v);
+            }
+        }
+        sC[wave * 64 + lane] = v;
+    }
+    __syncthreads();
+    if (tid < nk1) {
+        double g = 0.0;
+        for (int w = 0; w < kS2Waves; ++w) g += sC[w * 64 + tid];
+        double* gp = B.gpart + ((long)j * 4 + (pass * 2 + par)) * K * 2;
+        const int k = ctri(tid, k2);
+        gp[2 * k] = pass == 0 ? -g : g;
+        gp[2 * k + 1] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Self velocity-derivative table of the matrix-core path, written in the
+// padded row layout of each parity: s_pad[j][par][r][c] = S_self[g1 = par + 2r][g2 = c]
+// (zero beyond the triangle and at g = 0).  Workgroup = (row r, parity, vortex);
+// four lanes share one entry, each summing every fourth even-step m2.
+// ---------------------------------------------------------------------------
+constexpr int kSelfPadThreads = 512;
+__global__ __launch_bounds__(kSelfPadThreads) void k_self_pad(DevTables T, StageBufs B, int cur)
+{
+    const int M = T.M, K = T.K, GM = T.GM;
+    const int r = blockIdx.x, par = blockIdx.y & 1, j = blockIdx.y >> 1;
+    const S2Shape sh(M, par);
+    const int T0N = T.T0N, nt0 = (T0N + 1) * (T0N + 2) / 2;
+    extern __shared__ double sm_sp[];
+    double* sa = sm_sp;       // alpha [K]
+    double* th = sa + K;      // Psi0 [tri(T0N)]
+    const double* a = B.alpha[cur] + (long)j * K;
+    constexpr int kK = (MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 2) / 2;
+    constexpr int kT0 = ((3 * MMVM_MAX_ORDER + 1) / 2 + 2) * ((3 * MMVM_MAX_ORDER + 1) / 2 + 3) / 2;
+    constexpr int kSlots = (kK + kT0 + kSelfPadThreads - 1) / kSelfPadThreads;
+    double v[kSlots];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {  // clamped loads of both sources, selected afterwards
+        const int e = tid + kSelfPadThreads * q;
+        const double x = a[e < K ? e : 0];
+        const double y = T.t0_hi[(e >= K && e < K + nt0) ? e - K : 0];
+        v[q] = e < K ? x : y;
+    }
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+        const int e = tid + kSelfPadThreads * q;
+        if (e < K + nt0) sm_sp[e] = v[q];
+    }
+    __syncthreads();
+    const int g1 = par + 2 * r;
+    const int len = r < sh.nrp ? GM - g1 + 1 : 0;
+    double* out = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS + (long)r * sh.LDS;
+    for (int t = tid; t < 4 * sh.LDS; t += kSelfPadThreads) {
+        const int g2 = t >> 2, q = t & 3;
+        double acc = 0.0;
+        if (g2 < len && g1 + g2 > 0)
+            for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) {
+                const int b2 = (m2 + g2) >> 1;
+                for (int m1 = g1 & 1; m1 + m2 <= M; m1 += 2)
+                    acc = fma(sa[ctri(m1, m2)], th[ctri((m1 + g1) >> 1, b2)], acc);
+            }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (q == 0) out[g2] = acc;
+    }
+}
+
+hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipStream_t st)
+{
+    const S2Shape sh(T.M, 0);
+    const size_t shmem = sizeof(double) * ((size_t)T.K + (size_t)(T.T0N + 1) * (T.T0N + 2) / 2);
+    hipLaunchKernelGGL(k_self_pad, dim3(sh.RP, 2 * B.N), dim3(kSelfPadThreads), shmem, st, T, B, cur);
+    return hipGetLastError();
+}
+
+// Adds the four partial contractions of every moment, applies the projection
+// constant, the lambda scaling and the drift (eq:last_termsimp), and writes the
+// RHS or the RK4 update and the next stage's inputs.  One workgroup per vortex.
+template <class A>
+__global__ __launch_bounds__(256) void k_emit(DevTables T, StageBufs B, StageArgs S)
+{
+    typedef typename A::T R;
+    const int K = T.K, N = B.N, j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double red[16];
+    const double* al = B.alpha[S.cur] + (long)j * K;
+    const double* sp = N > 1 ? B.s_pair + (long)j * T.KG : nullptr;
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
     const double lam2n = B.lam0sq[j] + 4.0 * S.nu * S.t_next;
@@ -450,10 +792,7 @@ __global__ __launch_bounds__(512) void k_stage2(DevTables T, StageBufs B, StageA
         if (k == 0) val = 0.0;  // circulation is conserved exactly
         emit_moment(B, S, j, k, s, K, val, lam2n);
     }
-    if (tid == 0) {
-        emit_position(B, S, j, xd1, xd2, lam2n);
-        B.done[j] = 0u;  // ready for the next launch
-    }
+    if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,31 +973,48 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
         }
     }
     const int M1 = T.M + 1;
-    const int threads = 512;
-    const size_t elem = use_dd ? sizeof(dd) : sizeof(double);
-    // the factor slice goes to LDS when it fits (FP64 always does)
+    dim3 grid(4 * M1, B.N);
+    if (!use_dd) {
+        if (!stage2_uses_mfma(T.M, use_dd) || B.N != 1) return hipErrorInvalidValue;
+        const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
+        if (shmem > 64 * 1024) {
+            hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_mfma,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (ea != hipSuccess) {
+                (void)hipGetLastError();
+                report_hip_error(ea, "hipFuncSetAttribute(k_stage2_mfma dynamic LDS)");
+                return ea;
+            }
+        }
+        hipLaunchKernelGGL(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
+        return hipGetLastError();
+    }
+    // the factor slice goes to LDS when it fits
+    const size_t elem = sizeof(dd);
     const size_t base = (size_t)T.K + 2 * (size_t)T.KG + (size_t)M1 * M1;
     const bool fslice = (base + (size_t)M1 * M1) * elem <= 150 * 1024;
     const size_t shmem = elem * (base + (fslice ? (size_t)M1 * M1 : 0));
-    const void* fn = use_dd ? (fslice ? (const void*)k_stage2<ArithDD, true> : (const void*)k_stage2<ArithDD, false>)
-                            : (fslice ? (const void*)k_stage2<ArithF64, true> : (const void*)k_stage2<ArithF64, false>);
+    const void* fn = fslice ? (const void*)k_stage2_dd<true> : (const void*)k_stage2_dd<false>;
     if (shmem > 64 * 1024) {
         // large orders stage up to ~150 KB of LDS
         hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (ea != hipSuccess) {
             (void)hipGetLastError();
-            report_hip_error(ea, "hipFuncSetAttribute(k_stage2 dynamic LDS)");
+            report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
             return ea;
         }
     }
-    dim3 grid(4 * M1, B.N);
-    if (use_dd) {
-        if (fslice) hipLaunchKernelGGL((k_stage2<ArithDD, true>), grid, dim3(threads), shmem, st, T, B, A);
-        else hipLaunchKernelGGL((k_stage2<ArithDD, false>), grid, dim3(threads), shmem, st, T, B, A);
-    } else {
-        if (fslice) hipLaunchKernelGGL((k_stage2<ArithF64, true>), grid, dim3(threads), shmem, st, T, B, A);
-        else hipLaunchKernelGGL((k_stage2<ArithF64, false>), grid, dim3(threads), shmem, st, T, B, A);
-    }
+    if (fslice) hipLaunchKernelGGL((k_stage2_dd<true>), grid, dim3(512), shmem, st, T, B, A);
+    else hipLaunchKernelGGL((k_stage2_dd<false>), grid, dim3(512), shmem, st, T, B, A);
+    return hipGetLastError();
+}
+
+bool stage2_needs_emit(int M, bool dd) { return !stage2_fuses_self(M, dd); }
+
+hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
+{
+    if (use_dd) hipLaunchKernelGGL(k_emit<ArithDD>, dim3(B.N), dim3(256), 0, st, T, B, A);
+    else hipLaunchKernelGGL(k_emit<ArithF64>, dim3(B.N), dim3(256), 0, st, T, B, A);
     return hipGetLastError();
 }
 

@@ -15,6 +15,11 @@ struct DevTables {
     const double* f0_lo;
     const double* f1_hi;
     const double* f1_lo;
+    const double* binom;   // [M+1][M+1] C(l, i)
+    const double* fd0;     // [M+1][M+1] f0[k][i][i]
+    const double* fd1;     // [M+1][M+1] f1[k][i][i]
+    const double* wpad;    // matrix-core stage 2: banded factor operand [M+1][2][KA][LP] (k2, pass, g2, l2)
+    const double* cpad;    // matrix-core stage 2: C(l, i) zero-padded [LP][LP]
     const double* c1_hi;   // [K]
     const double* c1_lo;
     const double* kap0;    // [P+1][P+1]
@@ -41,8 +46,8 @@ struct StageBufs {
     double* s_self;        // [N][KG] self velocity-derivative table (lambda units)
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
+    double* s_pad;         // [N][2][RP][LDS] self table by rows of each parity, zero-padded (matrix-core path)
     double* gpart;         // [N][4][K][2] partial contractions of the large-order stage 2 (hi, lo)
-    unsigned* done;        // [N] workgroup counters of the large-order stage 2 (self-resetting)
     int* flag;             // device error flag (bit 0: zero circulation, bit 1: non-finite)
 };
 
@@ -76,9 +81,52 @@ hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32
 // orders whose stage-2 kernel computes the self table itself
 constexpr int kMaxSmallOrder = 10;
 bool stage2_fuses_self(int M, bool dd);
-// stage-2 contraction + drift + RK4 bookkeeping
+// stage-2 contraction; at small orders also the drift and the RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,
                          hipStream_t st);
+// large orders: the contraction writes four partial sums per moment and a
+// second kernel adds them and applies the drift and the RK4 bookkeeping
+bool stage2_needs_emit(int M, bool dd);
+hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd, hipStream_t st);
+
+// Matrix-core stage 2 (FP64, single vortex, orders kMaxSmallOrder + 1 .. kS2MaxOrder):
+// shapes of its zero-padded operands.  Rows r of the velocity-derivative table
+// hold g1 = par + 2r; l is padded to LP, g2 (the contraction index of the first
+// product) to KA, l of the second and third products to KBP <= LP.
+constexpr int kS2Threads = 512;
+constexpr int kS2Waves = kS2Threads / 64;
+constexpr int kS2MaxOrder = 47;
+constexpr int kS2TPad = 18;  // zero rows on either side of T
+bool stage2_uses_mfma(int M, bool dd);
+
+struct S2Shape {
+    int nrp, LP, RP, KA, KBP, LDS, LDY, LDT, NTR;
+    int r1, y, a2, cb, gd, total;  // LDS region offsets and size (doubles, multiples of 4)
+    __host__ __device__ S2Shape(int M, int par)
+    {
+        const int M1 = M + 1, GM = 2 * M;
+        nrp = (GM - par) / 2 + 1;
+        LP = 16 * ((M1 + 15) / 16);
+        RP = LP;                       // nrp <= M + 1 for either parity
+        KA = 4 * ((GM >> 2) + 1);
+        KBP = 4 * ((M >> 2) + 1);
+        LDS = KA + 1;                  // odd strides spread the rows over the LDS banks
+        LDY = LP + 1;
+        LDT = LP + 1;
+        NTR = GM + 1 + 2 * kS2TPad;
+        const int a_ops = RP * LDS + KA * LP;   // S rows and W (first product)
+        const int t_ops = NTR * LDT;            // T, sheared-friendly (second -> third product)
+        r1 = 0;
+        y = up4(a_ops > t_ops ? a_ops : t_ops);
+        a2 = y + up4(RP * LDY);
+        cb = a2 + up4(LP * LP);
+        gd = cb + up4(LP * LP > kS2Waves * 64 ? LP * LP : kS2Waves * 64);
+        total = gd + up4(M1 * M1);
+    }
+    __host__ __device__ static int up4(int n) { return (n + 3) & ~3; }
+    // per-vortex size of the padded self table (both parities)
+    __host__ __device__ int spad() const { return 2 * RP * LDS; }
+};
 
 // the pair kernel is compiled for orders 0..kMaxPairOrder
 constexpr int kMaxPairOrder = 6;

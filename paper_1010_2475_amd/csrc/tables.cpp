@@ -86,6 +86,21 @@ void build(Tables& T, int M)
                 }
             }
 
+    T.binom.assign((size_t)M1 * M1, 0.0);
+    for (int l = 0; l <= M; ++l) {
+        T.binom[(size_t)l * M1] = 1.0;
+        for (int i = 1; i <= l; ++i)
+            T.binom[(size_t)l * M1 + i] = T.binom[(size_t)(l - 1) * M1 + i - 1] + (i <= l - 1 ? T.binom[(size_t)(l - 1) * M1 + i] : 0.0);
+    }
+
+    T.fd0.assign((size_t)M1 * M1, 0.0);
+    T.fd1.assign((size_t)M1 * M1, 0.0);
+    for (int k = 0; k <= M; ++k)
+        for (int i = 0; i <= M; ++i) {
+            T.fd0[(size_t)k * M1 + i] = T.f0_hi[((size_t)k * M1 + i) * M1 + i];
+            T.fd1[(size_t)k * M1 + i] = T.f1_hi[((size_t)k * M1 + i) * M1 + i];
+        }
+
     // --- projection constants at lambda = 1
     T.c1_hi.assign(T.K, 0.0); T.c1_lo.assign(T.K, 0.0);
     for (int s = 0; s <= M; ++s)

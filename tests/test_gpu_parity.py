@@ -242,6 +242,30 @@ def test_single_random_order40_sampled_rows(env, orc, prec, tol):
     del ids
 
 
+@pytest.mark.parametrize("M", [11, 16, 24, 25, 33])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_particle_orders_sampled_rows(env, orc, M, prec):
+    """Orders between the small fused kernel and order 40: the matrix-core
+    contraction (FP64 up to order 24, and the mixed path at every order) and
+    the double-double contraction (FP64 above order 24), on rows spread over
+    the shells and the edges of the triangle."""
+    from paper_1010_2475_amd import workloads as wl
+    w = rand_workload(300 + M, 1, M)
+    t = 0.21
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    h = M // 2
+    rows = sorted({wl.index(1, 1), wl.index(0, M), wl.index(M, 0), wl.index(h, M - h), wl.index(3, 2),
+                   wl.index(M // 3, M // 3), wl.index(1, M - 1), wl.index(M - 2, 0), wl.index(2, h)})
+    d, _ = orc.rhs_rows(M, w.nu, w.lam0, t, w.x, w.mom, [0] * len(rows), rows)
+    lam = math.sqrt(w.lam0[0] ** 2 + 4 * w.nu * t)
+    n = _nk(M, lam)
+    scale = np.abs(dm_g[0] * n).max()
+    err = max(abs(dm_g[0, r] - d[i]) * n[r] for i, r in enumerate(rows)) / scale
+    tol = FP64_TOL if (M <= 24 or prec == 0) else 1e-9
+    assert err <= tol, err
+    assert dm_g[0, 0] == 0.0 and np.all(dx_g == 0.0)
+
+
 @pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
 def test_random_multi_64_sampled(env, orc, prec, tol):
     from paper_1010_2475_amd import workloads as wl
