@@ -99,6 +99,14 @@ mmvm_status device_tables(int M, const DevTables** out)
         }
         d.wpad = upload(*o, wpad, err);
         d.cpad = upload(*o, cpad, err);
+        std::vector<double> t0d;
+        if (stage2_uses_mfma(M, false)) {
+            const T0Shape tz(M);
+            t0d.assign((size_t)tz.T0R * tz.TP, 0.0);
+            for (int a = 0; a <= H.T0N; ++a)
+                for (int b = 0; a + b <= H.T0N; ++b) t0d[(size_t)a * tz.TP + b] = H.t0_hi[tri(a, b)];
+        }
+        d.t0d = upload(*o, t0d, err);
     }
     d.c1_hi = upload(*o, H.c1_hi, err);
     d.c1_lo = upload(*o, H.c1_lo, err);
@@ -129,8 +137,8 @@ void Workspace::release()
 
 namespace {
 struct Layout {
-    size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], sself, sselflo, spair, spad,
-        gpart, total;
+    size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
+        sselflo, spair, spad, gpart, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd)
 {
@@ -155,6 +163,10 @@ Layout layout_for(int N_, int M_, bool need_dd)
         L.alpha[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
+        const bool mx = stage2_uses_mfma(M_, false);
+        const S2Shape sh(M_, 0);
+        L.alphaD[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LA() * sh.LP : 0);
+        L.alphaS[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LP * sh.LP : 0);
     }
     L.sself = add(sizeof(double) * (size_t)N_ * KG);
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
@@ -207,6 +219,9 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         bufs.alpha[q] = (double*)(b + L.alpha[q]);
         bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
         bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
+        const bool mx = stage2_uses_mfma(M_, false);
+        bufs.alphaD[q] = mx ? (double*)(b + L.alphaD[q]) : nullptr;
+        bufs.alphaS[q] = mx ? (double*)(b + L.alphaS[q]) : nullptr;
     }
     bufs.s_self = (double*)(b + L.sself);
     bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;

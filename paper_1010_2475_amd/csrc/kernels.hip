@@ -33,7 +33,33 @@ __device__ __forceinline__ double inv_lambda_pow(double l2, int s)
     return p;
 }
 
-__global__ __launch_bounds__(256) void k_prep(int N, int K, const double* __restrict__ xin,
+// The two dense layouts of the scaled moments read by the matrix-core kernels
+// (only allocated on that path): alphaD[m1][m2] and (-1)^{|l|} alpha at (l2, l1).
+__device__ __forceinline__ void store_dense_alpha(const StageBufs& B, int buf, int M, int j, int k1, int k2, double a)
+{
+    if (!B.alphaD[buf]) return;
+    const int LP = 16 * ((M + 16) / 16), LA = LP + 16;
+    B.alphaD[buf][(long)j * LA * LP + k1 * LP + k2] = a;
+    B.alphaS[buf][(long)j * LP * LP + k2 * LP + k1] = ((k1 + k2) & 1) ? -a : a;
+}
+
+// zeros of the dense layouts outside the triangle, in both buffers
+__global__ __launch_bounds__(256) void k_alpha_dense_clear(StageBufs B, int M)
+{
+    const int LP = 16 * ((M + 16) / 16), LA = LP + 16;
+    const long per = (long)LA * LP, total = (long)B.N * per;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / per), pos = (int)(idx - (long)j * per);
+        const int m1 = pos / LP, m2 = pos - m1 * LP;
+        if (m1 + m2 <= M) continue;
+        for (int b = 0; b < 2; ++b) {
+            B.alphaD[b][idx] = 0.0;
+            if (m1 < LP) B.alphaS[b][(long)j * LP * LP + m2 * LP + m1] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N, int K, const double* __restrict__ xin,
                                               const double* __restrict__ min_, const double* __restrict__ lam0sq,
                                               double t, double nu, double* __restrict__ xs, double* __restrict__ ys,
                                               double* __restrict__ lam2, double* __restrict__ alpha,
@@ -45,9 +71,11 @@ __global__ __launch_bounds__(256) void k_prep(int N, int K, const double* __rest
         int j = (int)(idx / K), k = (int)(idx - (long)j * K);
         double l2 = lam0sq[j] + 4.0 * nu * t;
         double mk = min_[idx];
-        double a = mk * inv_lambda_pow(l2, shell_of(k));
+        const int sk = shell_of(k);
+        double a = mk * inv_lambda_pow(l2, sk);
         if (copy_state) ys[idx] = mk;
         alpha[idx] = a;
+        store_dense_alpha(B, cur, M, j, sk - (k - sk * (sk + 1) / 2), k - sk * (sk + 1) / 2, a);
         if (alphaT) alphaT[(long)k * N + j] = a;
         if (alphaT32) alphaT32[(long)k * N + j] = (float)a;
         if (!isfinite(mk)) atomicOr(flag, 2);
@@ -69,7 +97,14 @@ hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const do
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     bool copy = (min_ != B.ys);
-    hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
+    if (B.alphaD[0]) {
+        const int LP = 16 * ((T.M + 16) / 16);
+        long nz = (long)B.N * (LP + 16) * LP;
+        int zb = (int)((nz + 255) / 256);
+        if (zb > 4096) zb = 4096;
+        hipLaunchKernelGGL(k_alpha_dense_clear, dim3(zb), dim3(256), 0, st, B, T.M);
+    }
+    hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
                        B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
                        need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
     return hipGetLastError();
@@ -93,8 +128,8 @@ __device__ __forceinline__ double rk4_update(int stage, double dt, double* y, do
 
 // Emits dM^j_k/dt: RHS output, or the RK4 update plus the next stage's scaled
 // moment (and its source-major copies for the pair kernel).
-__device__ __forceinline__ void emit_moment(const StageBufs& B, const StageArgs& S, int j, int k, int s, int K,
-                                            double val, double lam2_next)
+__device__ __forceinline__ void emit_moment(const StageBufs& B, const StageArgs& S, int M, int j, int k, int s,
+                                            int K, double val, double lam2_next)
 {
     const long o = (long)j * K + k;
     if (S.mode == MODE_RHS) {
@@ -106,6 +141,10 @@ __device__ __forceinline__ void emit_moment(const StageBufs& B, const StageArgs&
     const int nx = 1 - S.cur;
     const double a = yn * inv_lambda_pow(lam2_next, s);
     B.alpha[nx][o] = a;
+    if (B.alphaD[nx]) {
+        const int k2 = k - s * (s + 1) / 2;
+        store_dense_alpha(B, nx, M, j, s - k2, k2, a);
+    }
     if (S.want_pair) {
         if (S.want_f32) B.alphaT32[nx][(long)k * B.N + j] = (float)a;
         else B.alphaT[nx][(long)k * B.N + j] = a;
@@ -528,22 +567,21 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     double* sC = smem + sh.cb;            // C(l, i) [LP][LP]              (C); then partial sums
     double* sG = smem + sh.gd;            // F'[k1][i][i] [M1][M1]         (last step)
 
-    // --- operands: contiguous copies (all loads of a thread issued first)
-    // plus the signed alpha triangle, zero-padded
+    // --- operands: contiguous copies, all loads of a thread issued first
     constexpr int kS2Rows = 16 * ((kS2MaxOrder + 16) / 16);
     constexpr int kSSlots = (kS2Rows * (4 * kS2KA + 1) / 2 + kS2Threads - 1) / kS2Threads;  // double2 of S
     constexpr int kWSlots = (4 * kS2KA * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;         // double2 of W
     constexpr int kCSlots = (kS2Rows * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;           // double2 of C
     constexpr int kDSlots = ((kS2MaxOrder + 1) * (kS2MaxOrder + 1) + kS2Threads - 1) / kS2Threads;
-    constexpr int kASlots = kS2Rows / kS2Waves;                                             // rows of alpha
+    constexpr int kASlots = (kS2Rows * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;           // double2 of alpha
     const double2* gS = reinterpret_cast<const double2*>(B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS);
     const double2* gW = reinterpret_cast<const double2*>(T.wpad + ((long)k2 * 2 + pass) * KA * LP);
     const double2* gC = reinterpret_cast<const double2*>(T.cpad);
+    const double2* gA = reinterpret_cast<const double2*>(B.alphaS[S.cur] + (long)j * LP * LP);
     const double* gD = pass == 0 ? T.fd1 : T.fd0;
-    const double* al = B.alpha[S.cur] + (long)j * K;
     const int nS2 = sh.RP * sh.LDS / 2, nW2 = KA * LP / 2, nC2 = LP * LP / 2, nD = M1 * M1;
-    double2 vS[kSSlots], vW[kWSlots], vC[kCSlots];
-    double vD[kDSlots], vA[kASlots];
+    double2 vS[kSSlots], vW[kWSlots], vC[kCSlots], vA[kASlots];
+    double vD[kDSlots];
 #pragma unroll
     for (int q = 0; q < kSSlots; ++q) {
         const int e = tid + kS2Threads * q;
@@ -558,20 +596,17 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     for (int q = 0; q < kCSlots; ++q) {
         const int e = tid + kS2Threads * q;
         vC[q] = gC[e < nC2 ? e : 0];
+        vA[q] = gA[e < nC2 ? e : 0];
     }
 #pragma unroll
     for (int q = 0; q < kDSlots; ++q) {
         const int e = tid + kS2Threads * q;
         vD[q] = gD[e < nD ? e : 0];
     }
-#pragma unroll
-    for (int q = 0; q < kASlots; ++q) {  // row l2 = wave + 8q, column l1 = lane
-        const int l2 = wave + kS2Waves * q;
-        vA[q] = al[lane + l2 <= M ? ctri(lane, l2) : 0];
-    }
     double2* dS = reinterpret_cast<double2*>(sS);
     double2* dW = reinterpret_cast<double2*>(sW);
     double2* dC = reinterpret_cast<double2*>(sC);
+    double2* dA = reinterpret_cast<double2*>(sA2);
 #pragma unroll
     for (int q = 0; q < kSSlots; ++q) {
         const int e = tid + kS2Threads * q;
@@ -585,17 +620,15 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
 #pragma unroll
     for (int q = 0; q < kCSlots; ++q) {
         const int e = tid + kS2Threads * q;
-        if (e < nC2) dC[e] = vC[q];
+        if (e < nC2) {
+            dC[e] = vC[q];
+            dA[e] = vA[q];
+        }
     }
 #pragma unroll
     for (int q = 0; q < kDSlots; ++q) {
         const int e = tid + kS2Threads * q;
         if (e < nD) sG[e] = vD[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kASlots; ++q) {
-        const int l2 = wave + kS2Waves * q;
-        if (l2 < LP && lane < LP) sA2[l2 * LP + lane] = lane + l2 <= M ? (((lane + l2) & 1) ? -vA[q] : vA[q]) : 0.0;
     }
     __syncthreads();
 
@@ -700,73 +733,102 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
 // ---------------------------------------------------------------------------
 // Self velocity-derivative table of the matrix-core path, written in the
 // padded row layout of each parity: s_pad[j][par][r][c] = S_self[g1 = par + 2r][g2 = c]
-// (zero beyond the triangle and at g = 0).  Workgroup = (row r, parity, vortex);
-// four lanes share one entry, each summing every fourth even-step m2.
+// (zero beyond the triangle and at g = 0).  Workgroup = (row r, parity, vortex).
+// With Psi0(2a, 2b) = t0[a][b] and m1 of the parity of g1 (m1 = p1 + 2 m1'):
+//   Q[m2][b]  = sum_{m1'} alpha[p1 + 2 m1'][m2] t0[m1' + ceil(g1 / 2)][b]   (matrix cores)
+//   S[g1][g2] = sum_{m2 = g2 mod 2} Q[m2][(m2 + g2) / 2].
 // ---------------------------------------------------------------------------
-constexpr int kSelfPadThreads = 512;
-__global__ __launch_bounds__(kSelfPadThreads) void k_self_pad(DevTables T, StageBufs B, int cur)
+constexpr int kSelfThreads = 512;
+constexpr int kSelfWaves = kSelfThreads / 64;
+__global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBufs B, int cur)
 {
-    const int M = T.M, K = T.K, GM = T.GM;
+    const int M = T.M, GM = T.GM;
     const int r = blockIdx.x, par = blockIdx.y & 1, j = blockIdx.y >> 1;
     const S2Shape sh(M, par);
-    const int T0N = T.T0N, nt0 = (T0N + 1) * (T0N + 2) / 2;
-    extern __shared__ double sm_sp[];
-    double* sa = sm_sp;       // alpha [K]
-    double* th = sa + K;      // Psi0 [tri(T0N)]
-    const double* a = B.alpha[cur] + (long)j * K;
-    constexpr int kK = (MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 2) / 2;
-    constexpr int kT0 = ((3 * MMVM_MAX_ORDER + 1) / 2 + 2) * ((3 * MMVM_MAX_ORDER + 1) / 2 + 3) / 2;
-    constexpr int kSlots = (kK + kT0 + kSelfPadThreads - 1) / kSelfPadThreads;
-    double v[kSlots];
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {  // clamped loads of both sources, selected afterwards
-        const int e = tid + kSelfPadThreads * q;
-        const double x = a[e < K ? e : 0];
-        const double y = T.t0_hi[(e >= K && e < K + nt0) ? e - K : 0];
-        v[q] = e < K ? x : y;
-    }
-#pragma unroll
-    for (int q = 0; q < kSlots; ++q) {
-        const int e = tid + kSelfPadThreads * q;
-        if (e < K + nt0) sm_sp[e] = v[q];
-    }
-    __syncthreads();
+    const T0Shape tz(M);
+    const int LP = sh.LP, TP = tz.TP, LDA = LP + 2, LDB = TP + 2, LDQ = TP + 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g1 = par + 2 * r;
     const int len = r < sh.nrp ? GM - g1 + 1 : 0;
     double* out = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS + (long)r * sh.LDS;
-    for (int t = tid; t < 4 * sh.LDS; t += kSelfPadThreads) {
+    if (len == 0) {
+        for (int c = tid; c < sh.LDS; c += kSelfThreads) out[c] = 0.0;
+        return;
+    }
+    const int p1 = g1 & 1, sh1 = (g1 + p1) >> 1;
+    const int ks = (((M - p1) >> 1) + 4) >> 2;  // m1' < 4 ks covers m1 <= M
+    extern __shared__ double smem[];
+    double* sAl = smem;                  // alpha rows m1 = p1 + 2 m1', [4 kSelfKS][LDA]
+    double* sT0 = sAl + 4 * kSelfKS * LDA;  // t0 rows sh1 + m1', [4 kSelfKS][LDB]
+    double* sQ = sT0 + 4 * kSelfKS * LDB;   // Q [LP][LDQ]
+
+    // operands: rows copied as double2, all loads first
+    constexpr int kRows = 4 * kSelfKS;
+    constexpr int kRowSlots = kRows / kSelfWaves;
+    static_assert(kRowSlots * kSelfWaves == kRows, "rows");
+    static_assert(16 * ((kS2MaxOrder + 16) / 16) / 2 <= 64, "alpha row fits a wavefront");
+    const double2* gA = reinterpret_cast<const double2*>(B.alphaD[cur] + (long)j * sh.LA() * LP);
+    const double2* gT = reinterpret_cast<const double2*>(T.t0d);
+    double2 va[kRowSlots], vt[kRowSlots];
+#pragma unroll
+    for (int q = 0; q < kRowSlots; ++q) {
+        const int m1p = wave + kSelfWaves * q;
+        const bool on = m1p < 4 * ks;  // rows of the k-steps in use (all inside both tables)
+        va[q] = gA[(on && lane < LP / 2) ? (p1 + 2 * m1p) * (LP / 2) + lane : 0];
+        vt[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < kRowSlots; ++q) {
+        const int m1p = wave + kSelfWaves * q;
+        if (lane < LP / 2) reinterpret_cast<double2*>(sAl + m1p * LDA)[lane] = va[q];
+        if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt[q];
+    }
+    __syncthreads();
+    // Q tiles: rows m2 < LP, columns b <= bmax
+    {
+        const int bmax = (M + len - 1) >> 1;
+        const int tr = LP >> 4, tc = (bmax >> 4) + 1;
+        const View va_ = {sAl, 1, LDA}, vb_ = {sT0, LDB, 1};
+        for (int t = wave; t < tr * tc; t += kSelfWaves) {
+            const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
+            const dbl4 d = mfma_tile<kSelfKS>(lane, r0, c0, 0, ks, va_, vb_);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sQ[(r0 + (lane >> 4) + 4 * q) * LDQ + c0 + (lane & 15)] = d[q];
+        }
+    }
+    __syncthreads();
+    // S[g1][g2] = sum over m2 of the parity of g2; four lanes per entry
+    for (int t = tid; t < 4 * sh.LDS; t += kSelfThreads) {
         const int g2 = t >> 2, q = t & 3;
         double acc = 0.0;
-        if (g2 < len && g1 + g2 > 0)
-            for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) {
-                const int b2 = (m2 + g2) >> 1;
-                for (int m1 = g1 & 1; m1 + m2 <= M; m1 += 2)
-                    acc = fma(sa[ctri(m1, m2)], th[ctri((m1 + g1) >> 1, b2)], acc);
-            }
+        if (g2 < len)
+            for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) acc += sQ[m2 * LDQ + ((m2 + g2) >> 1)];
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
-        if (q == 0) out[g2] = acc;
+        if (q == 0) out[g2] = (g2 < len && g1 + g2 > 0) ? acc : 0.0;
     }
 }
 
 hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipStream_t st)
 {
     const S2Shape sh(T.M, 0);
-    const size_t shmem = sizeof(double) * ((size_t)T.K + (size_t)(T.T0N + 1) * (T.T0N + 2) / 2);
-    hipLaunchKernelGGL(k_self_pad, dim3(sh.RP, 2 * B.N), dim3(kSelfPadThreads), shmem, st, T, B, cur);
+    const T0Shape tz(T.M);
+    const size_t shmem = sizeof(double) * (4 * (size_t)kSelfKS * ((sh.LP + 2) + (tz.TP + 2)) +
+                                           (size_t)sh.LP * (tz.TP + 1));
+    hipLaunchKernelGGL(k_self_mfma, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), shmem, st, T, B, cur);
     return hipGetLastError();
 }
 
-// Adds the four partial contractions of every moment, applies the projection
-// constant, the lambda scaling and the drift (eq:last_termsimp), and writes the
-// RHS or the RK4 update and the next stage's inputs.  One workgroup per vortex.
+constexpr int kEmitThreads = 1024;  // one moment per thread up to the largest order
+static_assert((MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 2) / 2 <= kEmitThreads, "emit");
+
 template <class A>
-__global__ __launch_bounds__(256) void k_emit(DevTables T, StageBufs B, StageArgs S)
+__global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B, StageArgs S)
 {
     typedef typename A::T R;
     const int K = T.K, N = B.N, j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    __shared__ double red[16];
+    __shared__ double red[2 * kEmitThreads / 64];
     const double* al = B.alpha[S.cur] + (long)j * K;
     const double* sp = N > 1 ? B.s_pair + (long)j * T.KG : nullptr;
     const double lam2 = B.lam2[S.cur][j];
@@ -790,7 +852,7 @@ __global__ __launch_bounds__(256) void k_emit(DevTables T, StageBufs B, StageArg
             if (kk2 >= 1) val += xd2 * al[ctri(k1, kk2 - 1)] * lq;
         }
         if (k == 0) val = 0.0;  // circulation is conserved exactly
-        emit_moment(B, S, j, k, s, K, val, lam2n);
+        emit_moment(B, S, T.M, j, k, s, K, val, lam2n);
     }
     if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
 }
@@ -922,7 +984,7 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
             if (k2 >= 1) val += xd2 * sAl[ctri(k1, k2 - 1)] * lq;
         }
         if (k == 0) val = 0.0;
-        emit_moment(B, S, j, k, s, K, val, lam2n);
+        emit_moment(B, S, T.M, j, k, s, K, val, lam2n);
     }
     if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
 }
@@ -1013,8 +1075,8 @@ bool stage2_needs_emit(int M, bool dd) { return !stage2_fuses_self(M, dd); }
 
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {
-    if (use_dd) hipLaunchKernelGGL(k_emit<ArithDD>, dim3(B.N), dim3(256), 0, st, T, B, A);
-    else hipLaunchKernelGGL(k_emit<ArithF64>, dim3(B.N), dim3(256), 0, st, T, B, A);
+    if (use_dd) hipLaunchKernelGGL(k_emit<ArithDD>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
+    else hipLaunchKernelGGL(k_emit<ArithF64>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
     return hipGetLastError();
 }
 

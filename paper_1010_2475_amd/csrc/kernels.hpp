@@ -20,6 +20,7 @@ struct DevTables {
     const double* fd1;     // [M+1][M+1] f1[k][i][i]
     const double* wpad;    // matrix-core stage 2: banded factor operand [M+1][2][KA][LP] (k2, pass, g2, l2)
     const double* cpad;    // matrix-core stage 2: C(l, i) zero-padded [LP][LP]
+    const double* t0d;     // matrix-core self table: Psi0 dense [T0R][TP] (a, b), zero beyond a + b <= T0N
     const double* c1_hi;   // [K]
     const double* c1_lo;
     const double* kap0;    // [P+1][P+1]
@@ -47,6 +48,8 @@ struct StageBufs {
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
     double* s_pad;         // [N][2][RP][LDS] self table by rows of each parity, zero-padded (matrix-core path)
+    double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
+    double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
     double* gpart;         // [N][4][K][2] partial contractions of the large-order stage 2 (hi, lo)
     int* flag;             // device error flag (bit 0: zero circulation, bit 1: non-finite)
 };
@@ -126,6 +129,21 @@ struct S2Shape {
     __host__ __device__ static int up4(int n) { return (n + 3) & ~3; }
     // per-vortex size of the padded self table (both parities)
     __host__ __device__ int spad() const { return 2 * RP * LDS; }
+    // rows of the dense alpha layout (zero rows beyond LP cover the k-steps of the self product)
+    __host__ __device__ int LA() const { return LP + 16; }
+};
+
+// Dense Psi0 operand of the matrix-core self table: columns b < TP, rows a < T0R.
+// The product for row g1 reads rows ceil(g1 / 2) .. ceil(g1 / 2) + 4 kSelfKS - 1.
+constexpr int kSelfKS = (kS2MaxOrder / 2 + 4) / 4;  // k-steps over m1 of one parity
+struct T0Shape {
+    int T0N, TP, T0R;
+    __host__ __device__ explicit T0Shape(int M)
+    {
+        T0N = (3 * M + 1) / 2 + 1;
+        TP = 16 * ((T0N + 1 + 15) / 16);
+        T0R = (2 * M + 1) / 2 + 4 * kSelfKS + 1;
+    }
 };
 
 // the pair kernel is compiled for orders 0..kMaxPairOrder
