@@ -107,6 +107,14 @@ mmvm_status device_tables(int M, const DevTables** out)
                 for (int b = 0; a + b <= H.T0N; ++b) t0d[(size_t)a * tz.TP + b] = H.t0_hi[tri(a, b)];
         }
         d.t0d = upload(*o, t0d, err);
+        std::vector<double> c1d;
+        if (stage2_uses_mfma(M, false)) {
+            const int LP = S2Shape(M, 0).LP;
+            c1d.assign((size_t)LP * LP, 0.0);
+            for (int k1 = 0; k1 <= M; ++k1)
+                for (int k2 = 0; k1 + k2 <= M; ++k2) c1d[(size_t)k1 * LP + k2] = H.c1_hi[tri(k1, k2)];
+        }
+        d.c1d = upload(*o, c1d, err);
     }
     d.c1_hi = upload(*o, H.c1_hi, err);
     d.c1_lo = upload(*o, H.c1_lo, err);
@@ -138,7 +146,7 @@ void Workspace::release()
 namespace {
 struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
-        sselflo, spair, spad, gpart, total;
+        sselflo, spair, spad, ystate[2], accd, gpartd, gpart, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd)
 {
@@ -172,6 +180,12 @@ Layout layout_for(int N_, int M_, bool need_dd)
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
     L.spad = add(stage2_uses_mfma(M_, false) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
+    {
+        const size_t dense = stage2_uses_mfma(M_, false) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
+        for (int b = 0; b < 2; ++b) L.ystate[b] = add(dense);
+        L.accd = add(dense);
+        L.gpartd = add(4 * dense);
+    }
     L.gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
     L.total = need;
     return L;
@@ -227,6 +241,12 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
     bufs.s_pair = (double*)(b + L.spair);
     bufs.s_pad = (double*)(b + L.spad);
+    {
+        const bool mx = stage2_uses_mfma(M_, false);
+        for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
+        bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
+        bufs.gpartD = mx ? (double*)(b + L.gpartd) : nullptr;
+    }
     bufs.gpart = (double*)(b + L.gpart);
     bufs.flag = (int*)(b + L.flag);
     flag_ptr = bufs.flag;

@@ -74,6 +74,10 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
         const int sk = shell_of(k);
         double a = mk * inv_lambda_pow(l2, sk);
         if (copy_state) ys[idx] = mk;
+        if (B.ystate[0]) {
+            const int LP = 16 * ((M + 16) / 16), k2 = k - sk * (sk + 1) / 2;
+            B.ystate[0][(long)j * LP * LP + (sk - k2) * LP + k2] = mk;
+        }
         alpha[idx] = a;
         store_dense_alpha(B, cur, M, j, sk - (k - sk * (sk + 1) / 2), k - sk * (sk + 1) / 2, a);
         if (alphaT) alphaT[(long)k * N + j] = a;
@@ -720,13 +724,10 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
         sC[wave * 64 + lane] = v;
     }
     __syncthreads();
-    if (tid < nk1) {
+    if (tid < nk1) {  // partial G[k1 = tid][k2] of this (pass, parity), dense layout
         double g = 0.0;
         for (int w = 0; w < kS2Waves; ++w) g += sC[w * 64 + tid];
-        double* gp = B.gpart + ((long)j * 4 + (pass * 2 + par)) * K * 2;
-        const int k = ctri(tid, k2);
-        gp[2 * k] = pass == 0 ? -g : g;
-        gp[2 * k + 1] = 0.0;
+        B.gpartD[((long)j * 4 + (pass * 2 + par)) * LP * LP + tid * LP + k2] = pass == 0 ? -g : g;
     }
 }
 
@@ -740,7 +741,8 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
 // ---------------------------------------------------------------------------
 constexpr int kSelfThreads = 512;
 constexpr int kSelfWaves = kSelfThreads / 64;
-__global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBufs B, int cur)
+template <bool APPLY>
+__global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBufs B, int cur, ApplyArgs P)
 {
     const int M = T.M, GM = T.GM;
     const int r = blockIdx.x, par = blockIdx.y & 1, j = blockIdx.y >> 1;
@@ -751,38 +753,105 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g1 = par + 2 * r;
     const int len = r < sh.nrp ? GM - g1 + 1 : 0;
+    const int p1 = g1 & 1, sh1 = (g1 + p1) >> 1;
+    const int ks = (((M - p1) >> 1) + 4) >> 2;  // m1' < 4 ks covers m1 <= M
     double* out = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS + (long)r * sh.LDS;
-    if (len == 0) {
+    if (len == 0 && r != 0) {  // rows beyond the triangle
         for (int c = tid; c < sh.LDS; c += kSelfThreads) out[c] = 0.0;
         return;
     }
-    const int p1 = g1 & 1, sh1 = (g1 + p1) >> 1;
-    const int ks = (((M - p1) >> 1) + 4) >> 2;  // m1' < 4 ks covers m1 <= M
     extern __shared__ double smem[];
     double* sAl = smem;                  // alpha rows m1 = p1 + 2 m1', [4 kSelfKS][LDA]
     double* sT0 = sAl + 4 * kSelfKS * LDA;  // t0 rows sh1 + m1', [4 kSelfKS][LDB]
     double* sQ = sT0 + 4 * kSelfKS * LDB;   // Q [LP][LDQ]
-
-    // operands: rows copied as double2, all loads first
     constexpr int kRows = 4 * kSelfKS;
     constexpr int kRowSlots = kRows / kSelfWaves;
     static_assert(kRowSlots * kSelfWaves == kRows, "rows");
-    static_assert(16 * ((kS2MaxOrder + 16) / 16) / 2 <= 64, "alpha row fits a wavefront");
-    const double2* gA = reinterpret_cast<const double2*>(B.alphaD[cur] + (long)j * sh.LA() * LP);
+    static_assert(16 * ((kS2MaxOrder + 16) / 16) <= 64, "a row of alpha fits a wavefront");
+
     const double2* gT = reinterpret_cast<const double2*>(T.t0d);
-    double2 va[kRowSlots], vt[kRowSlots];
+    if constexpr (APPLY) {
+        // finish the previous stage for the moments with m1 of this parity; the
+        // row-0 workgroup of each parity writes their state and signed moments.
+        // All loads first; the powers of lambda come from a table built with
+        // the same sequential products as the emit kernel.
+        const double wts[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+        const double cn[3] = {0.5, 0.5, 1.0};
+        const int K = T.K;
+        const bool writer = r == 0;
+        const bool need_acc = P.stage == 3 || (writer && P.stage > 0);
+        double2 vt2[kRowSlots];
+        double pg[kRowSlots][4], pc[kRowSlots], py[kRowSlots], pa[kRowSlots];
+        const long LL = (long)LP * LP;
+        const double* gpj = B.gpartD + (long)j * 4 * LL;
+        const double* yj = B.ystate[P.ycur] + (long)j * LL;
+        const double* aj = B.accD + (long)j * LL;
 #pragma unroll
-    for (int q = 0; q < kRowSlots; ++q) {
-        const int m1p = wave + kSelfWaves * q;
-        const bool on = m1p < 4 * ks;  // rows of the k-steps in use (all inside both tables)
-        va[q] = gA[(on && lane < LP / 2) ? (p1 + 2 * m1p) * (LP / 2) + lane : 0];
-        vt[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
-    }
+        for (int q = 0; q < kRowSlots; ++q) {
+            const int m1p = wave + kSelfWaves * q, m1 = p1 + 2 * m1p, m2 = lane;
+            const bool on = m1p < 4 * ks;
+            vt2[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
+            const int d = m1 + m2 <= M ? m1 * LP + m2 : 0;  // dense (k1, k2) position
 #pragma unroll
-    for (int q = 0; q < kRowSlots; ++q) {
-        const int m1p = wave + kSelfWaves * q;
-        if (lane < LP / 2) reinterpret_cast<double2*>(sAl + m1p * LDA)[lane] = va[q];
-        if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt[q];
+            for (int h = 0; h < 4; ++h) pg[q][h] = gpj[h * LL + d];
+            pc[q] = T.c1d[d];
+            py[q] = yj[d];
+            pa[q] = need_acc ? aj[d] : 0.0;
+        }
+        __shared__ double pw[2][MMVM_MAX_ORDER + 1];  // lambda_prev^s / lambda_prev^2, lambda_next^{-s}
+        if (tid <= M) {
+            const double lam2p = B.lam0sq[j] + 4.0 * P.nu * P.t_prev;
+            const double lamp = sqrt(lam2p);
+            const double lam2n = B.lam0sq[j] + 4.0 * P.nu * P.t_next;
+            double lp = 1.0;
+            for (int e = 0; e < tid; ++e) lp *= lamp;
+            pw[0][tid] = lp / lam2p;
+            pw[1][tid] = inv_lambda_pow(lam2n, tid);
+            if (writer && par == 0 && tid == 0) B.lam2[cur][j] = lam2n;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRowSlots; ++q) {
+            const int m1p = wave + kSelfWaves * q, m1 = p1 + 2 * m1p, m2 = lane;
+            double a = 0.0;
+            if (m1 + m2 <= M) {
+                const int s = m1 + m2, k = ctri(m1, m2);
+                double g = pg[q][0] + pg[q][1];
+                g += pg[q][2];
+                g += pg[q][3];
+                const double val = k == 0 ? 0.0 : (pc[q] * g) * pw[0][s];  // circulation is conserved exactly
+                double nxt;
+                const long o = (long)j * LL + m1 * LP + m2;
+                if (P.stage < 3) {
+                    if (writer) B.accD[o] = P.stage == 0 ? wts[0] * val : pa[q] + wts[P.stage] * val;
+                    nxt = py[q] + cn[P.stage] * P.dt * val;
+                } else {
+                    nxt = py[q] + P.dt * (pa[q] + wts[3] * val);
+                    if (writer) B.ystate[1 - P.ycur][o] = nxt;
+                }
+                a = nxt * pw[1][s];
+                if (writer) B.alphaS[cur][(long)j * LP * LP + m2 * LP + m1] = (s & 1) ? -a : a;
+            }
+            if (lane < LP) sAl[m1p * LDA + lane] = a;
+            if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt2[q];
+        }
+    } else {
+        // operands: rows copied as double2, all loads first
+        const double2* gA = reinterpret_cast<const double2*>(B.alphaD[cur] + (long)j * sh.LA() * LP);
+        double2 va[kRowSlots], vt[kRowSlots];
+#pragma unroll
+        for (int q = 0; q < kRowSlots; ++q) {
+            const int m1p = wave + kSelfWaves * q;
+            const bool on = m1p < 4 * ks;  // rows of the k-steps in use (all inside both tables)
+            va[q] = gA[(on && lane < LP / 2) ? (p1 + 2 * m1p) * (LP / 2) + lane : 0];
+            vt[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < kRowSlots; ++q) {
+            const int m1p = wave + kSelfWaves * q;
+            if (lane < LP / 2) reinterpret_cast<double2*>(sAl + m1p * LDA)[lane] = va[q];
+            if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt[q];
+        }
     }
     __syncthreads();
     // Q tiles: rows m2 < LP, columns b <= bmax
@@ -810,13 +879,60 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     }
 }
 
+static size_t self_mfma_lds(int M)
+{
+    const S2Shape sh(M, 0);
+    const T0Shape tz(M);
+    return sizeof(double) * (4 * (size_t)kSelfKS * ((sh.LP + 2) + (tz.TP + 2)) + (size_t)sh.LP * (tz.TP + 1));
+}
+
+bool stage2_fuses_emit(int M, bool dd, int N) { return stage2_uses_mfma(M, dd) && N == 1; }
+
+hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st)
+{
+    const S2Shape sh(T.M, 0);
+    hipLaunchKernelGGL(k_self_mfma<true>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
+                       cur, P);
+    return hipGetLastError();
+}
+
+// the last stage of a stepping call: y_{n+1} into the caller's moments (same
+// arithmetic, in the same order, as the emit kernel)
+__global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, ApplyArgs P)
+{
+    const int j = blockIdx.x, K = T.K;
+    const int LP = 16 * ((T.M + 16) / 16);
+    const long LL = (long)LP * LP;
+    const double lam2p = B.lam0sq[j] + 4.0 * P.nu * P.t_prev;
+    const double lamp = sqrt(lam2p);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const int s = shell_of(k);
+        const int k2 = k - s * (s + 1) / 2, k1 = s - k2;
+        const long o = (long)j * LL + k1 * LP + k2;
+        const double* gp = B.gpartD + (long)j * 4 * LL + k1 * LP + k2;
+        double g = gp[0] + gp[LL];
+        g += gp[2 * LL];
+        g += gp[3 * LL];
+        double lp = 1.0;  // lambda^{s-2}
+        for (int e = 0; e < s; ++e) lp *= lamp;
+        lp /= lam2p;
+        const double val = k == 0 ? 0.0 : (T.c1d[k1 * LP + k2] * g) * lp;
+        P.mom_out[(long)j * K + k] = B.ystate[P.ycur][o] + P.dt * (B.accD[o] + (1.0 / 6.0) * val);
+    }
+}
+
+hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_apply_final, dim3(B.N), dim3(1024), 0, st, T, B, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipStream_t st)
 {
     const S2Shape sh(T.M, 0);
-    const T0Shape tz(T.M);
-    const size_t shmem = sizeof(double) * (4 * (size_t)kSelfKS * ((sh.LP + 2) + (tz.TP + 2)) +
-                                           (size_t)sh.LP * (tz.TP + 1));
-    hipLaunchKernelGGL(k_self_mfma, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), shmem, st, T, B, cur);
+    ApplyArgs none{};
+    hipLaunchKernelGGL(k_self_mfma<false>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
+                       cur, none);
     return hipGetLastError();
 }
 
@@ -837,11 +953,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
     double xd1 = 0.0, xd2 = 0.0;
     if (N > 1) centre_velocity(al, sp, K, lam, red, xd1, xd2);
     const double* gj = B.gpart + (long)j * 4 * K * 2;
+    const int LP = 16 * ((T.M + 16) / 16);
     for (int k = tid; k < K; k += nt) {
-        R g = A::zero();
-        for (int q = 0; q < 4; ++q) g = A::add(g, A::ldst(gj + ((long)q * K + k) * 2));
         const int s = shell_of(k);
         const int kk2 = k - s * (s + 1) / 2, k1 = s - kk2;
+        R g = A::zero();
+        if constexpr (std::is_same<A, ArithF64>::value) {  // the matrix-core contraction: dense partials
+            const double* gd = B.gpartD + (long)j * 4 * LP * LP + k1 * LP + kk2;
+            for (int q = 0; q < 4; ++q) g = A::add(g, gd[(long)q * LP * LP]);
+        } else {
+            for (int q = 0; q < 4; ++q) g = A::add(g, A::ldst(gj + ((long)q * K + k) * 2));
+        }
         double lp = 1.0;  // lambda^{s-2}
         for (int e = 0; e < s; ++e) lp *= lam;
         lp /= lam2;

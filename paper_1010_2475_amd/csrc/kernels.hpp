@@ -21,6 +21,7 @@ struct DevTables {
     const double* wpad;    // matrix-core stage 2: banded factor operand [M+1][2][KA][LP] (k2, pass, g2, l2)
     const double* cpad;    // matrix-core stage 2: C(l, i) zero-padded [LP][LP]
     const double* t0d;     // matrix-core self table: Psi0 dense [T0R][TP] (a, b), zero beyond a + b <= T0N
+    const double* c1d;     // matrix-core path: c1 dense [LP][LP] (k1, k2)
     const double* c1_hi;   // [K]
     const double* c1_lo;
     const double* kap0;    // [P+1][P+1]
@@ -50,6 +51,10 @@ struct StageBufs {
     double* s_pad;         // [N][2][RP][LDS] self table by rows of each parity, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
+    // matrix-core path, dense (k1, k2) layouts [N][LP][LP]:
+    double* gpartD;        // [N][4][LP][LP] partial contractions of stage 2
+    double* ystate[2];     // RK4 state y_n, alternating by step (single-vortex stepping)
+    double* accD;          // RK4 accumulator (single-vortex stepping)
     double* gpart;         // [N][4][K][2] partial contractions of the large-order stage 2 (hi, lo)
     int* flag;             // device error flag (bit 0: zero circulation, bit 1: non-finite)
 };
@@ -79,6 +84,23 @@ hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const do
                        double t, double nu, bool need_pair, bool need_f32, hipStream_t st);
 // self velocity-derivative table (orders without a fused self term); dd = double-double
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st);
+
+// Matrix-core RK4 stepping of one vortex: the self kernel of stage t + 1 first
+// finishes stage t from its partial contractions (RK4 update of the state held
+// in ystate[ycur], scaled moments of stage t + 1 built in LDS; the row-0
+// workgroups write the state, the accumulators and the signed moments of
+// stage2); the last stage of a call is finished by launch_apply_final.
+struct ApplyArgs {
+    int stage;         // RK4 stage t whose partial sums are applied
+    int ycur;          // ystate[ycur] holds y_n
+    double t_prev;     // time of stage t
+    double t_next;     // time of stage t + 1
+    double dt, nu;
+    double* mom_out;   // launch_apply_final: y_{n+1} -> the caller's moments
+};
+bool stage2_fuses_emit(int M, bool dd, int N);
+hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st);
+hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st);
 // pair velocity-derivative table (N > 1); f32 = mixed precision
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 // orders whose stage-2 kernel computes the self table itself

@@ -185,9 +185,13 @@ class Server:
                              ctypes.byref(st))
         if rc == PENDING:
             return None
-        _check(rc, "mmvm_poll")
-        return x, mom, {"t_arrive": st.t_arrive, "t_admit": st.t_admit, "t_start": st.t_start,
-                        "t_done": st.t_done, "steps": st.steps}
+        stats = {"t_arrive": st.t_arrive, "t_admit": st.t_admit, "t_start": st.t_start, "t_done": st.t_done,
+                 "steps": st.steps}
+        if rc != OK:
+            err = MMVMError(rc, "mmvm_poll")
+            err.stats = stats  # the request's timeline up to the error
+            raise err
+        return x, mom, stats
 
     def drain(self):
         _check(lib().mmvm_server_drain(self._h), "mmvm_server_drain")

@@ -204,6 +204,57 @@ def test_step_matches_oracle(env, orc, N, M, steps):
         assert np.array_equal(m_g[:, 0], w.mom[:, 0])  # circulation bitwise
 
 
+def host_rk4_via_rhs(env, w, t0, nsteps, prec):
+    """Classic RK4 driven from the host, one mmvm_rhs per stage, combined with
+    the same operations in the same order as the device stepper."""
+    torch, mm = env
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.x, dtype=torch.float64, device=dev).contiguous()
+    Y = torch.tensor(w.mom, dtype=torch.float64, device=dev).contiguous()
+    c = (0.0, 0.5, 0.5, 1.0)
+    wts = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
+    for n in range(nsteps):
+        Ys, acc = Y, None
+        for s in range(4):
+            dX, dM = torch.zeros_like(X), torch.zeros_like(Y)
+            mm.rhs(w.M, w.nu, w.lam0, t0 + (n + c[s]) * w.dt, X, Ys.contiguous(), dX, dM, prec)
+            if s < 3:
+                acc = wts[0] * dM if s == 0 else acc + wts[s] * dM
+                Ys = Y + (c[s + 1] * w.dt) * dM
+            else:
+                Y = Y + w.dt * (acc + wts[3] * dM)
+    mm.sync()
+    return Y.cpu().numpy()
+
+
+@pytest.mark.parametrize("M,prec", [(12, 0), (17, 1), (24, 0), (40, 1), (40, 0)])
+def test_large_order_step_matches_rhs_driven_rk4(env, M, prec):
+    """Single-vortex stepping at large orders (the matrix-core path finishes
+    each stage inside the next stage's self kernel; the double-double path
+    uses the emit kernel) against RK4 assembled on the host from mmvm_rhs."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=M, Re=500.0)
+    w.dt = 2e-3
+    _, m_g = gpu_step(env, w, 0.05, 3, prec)
+    m_h = host_rk4_via_rhs(env, w, 0.05, 3, prec)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * (0.05 + 3 * w.dt))
+    assert normwise(M, lam_t, m_h, m_g) <= 1e-13
+    assert m_g[0, 0] == w.mom[0, 0]
+
+
+def test_large_order_step_matches_oracle(env, orc):
+    """Order 12, two RK4 steps of one vortex against the oracle's RK4."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=12, Re=300.0)
+    w.dt = 5e-3
+    x_r, m_r = orc.rk4(w.M, w.nu, w.lam0, 0.1, w.dt, 2, w.x, w.mom)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * (0.1 + 2 * w.dt))
+    for prec in (0, 1):
+        x_g, m_g = gpu_step(env, w, 0.1, 2, prec)
+        assert normwise(w.M, lam_t, m_r, m_g) <= FP64_TOL
+        assert np.all(x_g == w.x)
+
+
 # ---------------------------------------------------------------------------
 # the workloads at full size (sampled outputs the oracle computes one by one)
 # ---------------------------------------------------------------------------
