@@ -218,8 +218,9 @@ def main():
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
                      "flops_per_launch": flops[dom], "avg_launch_ms": avg_ms,
-                     "note": "algorithmic flops of the factorised contraction of one vortex per launch; "
-                             "duration from HIP events around each launch on its stream"},
+                     "note": "algorithmic flops of the factorised contraction of one vortex per launch (the "
+                             "matrix-core kernel also multiplies the zero padding of its operands); duration "
+                             "from runtime-stamped start/end events of each launch on its stream"},
     }
 
     if args.serve_requests > 0:

@@ -101,16 +101,16 @@ hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const do
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     bool copy = (min_ != B.ys);
-    if (B.alphaD[0]) {
+    launch_kernel(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
+                       B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
+                       need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
+    if (B.alphaD[0]) {  // zeros of the dense layouts (disjoint from what k_prep writes)
         const int LP = 16 * ((T.M + 16) / 16);
         long nz = (long)B.N * (LP + 16) * LP;
         int zb = (int)((nz + 255) / 256);
         if (zb > 4096) zb = 4096;
-        hipLaunchKernelGGL(k_alpha_dense_clear, dim3(zb), dim3(256), 0, st, B, T.M);
+        launch_kernel(k_alpha_dense_clear, dim3(zb), dim3(256), 0, st, B, T.M);
     }
-    hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
-                       B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
-                       need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -245,10 +245,10 @@ hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd,
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
     size_t shmem = sizeof(double) * ((size_t)T.K + (dd ? 2 : 1) * (size_t)nt0);
     if (dd)
-        hipLaunchKernelGGL(k_self<true>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
+        launch_kernel(k_self<true>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
                            B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, B.s_self_lo);
     else
-        hipLaunchKernelGGL(k_self<false>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
+        launch_kernel(k_self<false>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
                            B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, (double*)nullptr);
     return hipGetLastError();
 }
@@ -891,7 +891,7 @@ bool stage2_fuses_emit(int M, bool dd, int N) { return stage2_uses_mfma(M, dd) &
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st)
 {
     const S2Shape sh(T.M, 0);
-    hipLaunchKernelGGL(k_self_mfma<true>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
+    launch_kernel(k_self_mfma<true>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
                        cur, P);
     return hipGetLastError();
 }
@@ -923,7 +923,7 @@ __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, 
 
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_apply_final, dim3(B.N), dim3(1024), 0, st, T, B, P);
+    launch_kernel(k_apply_final, dim3(B.N), dim3(1024), 0, st, T, B, P);
     return hipGetLastError();
 }
 
@@ -931,7 +931,7 @@ hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipS
 {
     const S2Shape sh(T.M, 0);
     ApplyArgs none{};
-    hipLaunchKernelGGL(k_self_mfma<false>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
+    launch_kernel(k_self_mfma<false>, dim3(sh.RP, 2 * B.N), dim3(kSelfThreads), self_mfma_lds(T.M), st, T, B,
                        cur, none);
     return hipGetLastError();
 }
@@ -1134,7 +1134,7 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
             return ea;
         }
     }
-    hipLaunchKernelGGL(k_stage2_small<M>, dim3(B.N), dim3(threads), shmem, st, T, B, A);
+    launch_kernel(k_stage2_small<M>, dim3(B.N), dim3(threads), shmem, st, T, B, A);
     return hipGetLastError();
 }
 
@@ -1170,7 +1170,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
                 return ea;
             }
         }
-        hipLaunchKernelGGL(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
+        launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();
     }
     // the factor slice goes to LDS when it fits
@@ -1188,8 +1188,8 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
             return ea;
         }
     }
-    if (fslice) hipLaunchKernelGGL((k_stage2_dd<true>), grid, dim3(512), shmem, st, T, B, A);
-    else hipLaunchKernelGGL((k_stage2_dd<false>), grid, dim3(512), shmem, st, T, B, A);
+    if (fslice) launch_kernel((k_stage2_dd<true>), grid, dim3(512), shmem, st, T, B, A);
+    else launch_kernel((k_stage2_dd<false>), grid, dim3(512), shmem, st, T, B, A);
     return hipGetLastError();
 }
 
@@ -1197,8 +1197,8 @@ bool stage2_needs_emit(int M, bool dd) { return !stage2_fuses_self(M, dd); }
 
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {
-    if (use_dd) hipLaunchKernelGGL(k_emit<ArithDD>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
-    else hipLaunchKernelGGL(k_emit<ArithF64>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
+    if (use_dd) launch_kernel(k_emit<ArithDD>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
+    else launch_kernel(k_emit<ArithF64>, dim3(B.N), dim3(kEmitThreads), 0, st, T, B, A);
     return hipGetLastError();
 }
 

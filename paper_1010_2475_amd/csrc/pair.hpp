@@ -218,10 +218,10 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     const int wpb = 4;
     dim3 grid((B.N + wpb - 1) / wpb);
     if (f32)
-        hipLaunchKernelGGL((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT32[cur], T.kap0,
+        launch_kernel((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT32[cur], T.kap0,
                            T.kap1, T.hol, T.rcp, B.s_pair);
     else
-        hipLaunchKernelGGL((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT[cur], T.kap0,
+        launch_kernel((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT[cur], T.kap0,
                            T.kap1, T.hol, T.rcp, B.s_pair);
     return hipGetLastError();
 }

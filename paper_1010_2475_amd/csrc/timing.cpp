@@ -1,4 +1,5 @@
-// Optional per-kernel timing with HIP events recorded on the launch stream.
+// Optional per-kernel timing: events stamped at the start and end of the timed
+// kernel by the runtime (hipExtLaunchKernel), on the kernel's own stream.
 #include <map>
 #include <mutex>
 #include <string>
@@ -51,6 +52,12 @@ void collect_locked()
 }
 }  // namespace
 
+TimingSlot*& timing_slot()
+{
+    static thread_local TimingSlot* slot = nullptr;
+    return slot;
+}
+
 bool timing_on()
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -59,21 +66,31 @@ bool timing_on()
 
 void* timing_begin(hipStream_t st)
 {
+    (void)st;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return nullptr;
-    hipEvent_t a = get_event();
-    (void)hipEventRecord(a, st);
-    return (void*)a;
+    TimingSlot* ts = new TimingSlot();
+    ts->start = get_event();
+    ts->stop = get_event();
+    timing_slot() = ts;
+    return ts;
 }
 
 void timing_end(void* tok, const char* name, hipStream_t st)
 {
+    (void)st;
     if (!tok) return;
+    TimingSlot* ts = (TimingSlot*)tok;
+    timing_slot() = nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
-    hipEvent_t b = get_event();
-    (void)hipEventRecord(b, st);
-    g_pending.push_back(Pending{name, (hipEvent_t)tok, b});
-    if (g_pending.size() > 4096) collect_locked();
+    if (ts->used) {
+        g_pending.push_back(Pending{name, ts->start, ts->stop});
+        if (g_pending.size() > 4096) collect_locked();
+    } else {
+        g_pool.push_back(ts->start);
+        g_pool.push_back(ts->stop);
+    }
+    delete ts;
 }
 
 }  // namespace mmvm
