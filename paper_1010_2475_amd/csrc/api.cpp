@@ -78,7 +78,7 @@ mmvm_status device_tables(int M, const DevTables** out)
     {
         // zero-padded operands of the matrix-core stage 2 (see S2Shape)
         std::vector<double> wpad, cpad;
-        if (stage2_uses_mfma(M, false)) {
+        if (mfma_order(M)) {
             const S2Shape sh(M, 0);
             const int M1 = M + 1, KA = sh.KA, LP = sh.LP;
             wpad.assign((size_t)M1 * 2 * KA * LP, 0.0);
@@ -100,7 +100,7 @@ mmvm_status device_tables(int M, const DevTables** out)
         d.wpad = upload(*o, wpad, err);
         d.cpad = upload(*o, cpad, err);
         std::vector<double> t0d;
-        if (stage2_uses_mfma(M, false)) {
+        if (mfma_order(M)) {
             const T0Shape tz(M);
             t0d.assign((size_t)tz.T0R * tz.TP, 0.0);
             for (int a = 0; a <= H.T0N; ++a)
@@ -108,7 +108,7 @@ mmvm_status device_tables(int M, const DevTables** out)
         }
         d.t0d = upload(*o, t0d, err);
         std::vector<double> c1d;
-        if (stage2_uses_mfma(M, false)) {
+        if (mfma_order(M)) {
             const int LP = S2Shape(M, 0).LP;
             c1d.assign((size_t)LP * LP, 0.0);
             for (int k1 = 0; k1 <= M; ++k1)
@@ -124,6 +124,8 @@ mmvm_status device_tables(int M, const DevTables** out)
     std::vector<double> rcp(128, 0.0);
     for (int i = 1; i < 128; ++i) rcp[i] = 1.0 / (double)i;
     d.rcp = upload(*o, rcp, err);
+    // the tables are read by kernels on any (possibly non-blocking) stream
+    if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err != hipSuccess) {
         report_hip_error(err, "table upload");
         return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
@@ -171,7 +173,7 @@ Layout layout_for(int N_, int M_, bool need_dd)
         L.alpha[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
-        const bool mx = stage2_uses_mfma(M_, false);
+        const bool mx = stage2_uses_mfma(M_, false, N_);
         const S2Shape sh(M_, 0);
         L.alphaD[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LA() * sh.LP : 0);
         L.alphaS[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LP * sh.LP : 0);
@@ -179,9 +181,9 @@ Layout layout_for(int N_, int M_, bool need_dd)
     L.sself = add(sizeof(double) * (size_t)N_ * KG);
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
-    L.spad = add(stage2_uses_mfma(M_, false) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
+    L.spad = add(stage2_uses_mfma(M_, false, N_) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
-        const size_t dense = stage2_uses_mfma(M_, false) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
+        const size_t dense = stage2_uses_mfma(M_, false, N_) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
         for (int b = 0; b < 2; ++b) L.ystate[b] = add(dense);
         L.accd = add(dense);
         L.gpartd = add(4 * dense);
@@ -216,7 +218,10 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         }
         base = (char*)p;
         bytes = need;
-        if (hipMemset(base, 0, need) != hipSuccess) return MMVM_EDEVICE;  // the error flag starts at 0
+        // zeroed on the workspace's stream (the error flag starts at 0): a plain
+        // hipMemset runs on the null stream, which does not order work on
+        // non-blocking streams
+        if (hipMemsetAsync(base, 0, need, st) != hipSuccess) return MMVM_EDEVICE;
         lam0_cache.clear();
     }
     N = N_;
@@ -233,7 +238,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         bufs.alpha[q] = (double*)(b + L.alpha[q]);
         bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
         bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
-        const bool mx = stage2_uses_mfma(M_, false);
+        const bool mx = stage2_uses_mfma(M_, false, N_);
         bufs.alphaD[q] = mx ? (double*)(b + L.alphaD[q]) : nullptr;
         bufs.alphaS[q] = mx ? (double*)(b + L.alphaS[q]) : nullptr;
     }
@@ -242,7 +247,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.s_pair = (double*)(b + L.spair);
     bufs.s_pad = (double*)(b + L.spad);
     {
-        const bool mx = stage2_uses_mfma(M_, false);
+        const bool mx = stage2_uses_mfma(M_, false, N_);
         for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
         bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
         bufs.gpartD = mx ? (double*)(b + L.gpartd) : nullptr;
@@ -316,7 +321,7 @@ mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, con
     const bool dd = use_dd(T.M, prec);
     hipError_t e;
     void* tk;
-    if (!stage2_fuses_self(T.M, dd)) {
+    if (!stage2_fuses_self(T.M, dd, W.bufs.N)) {
         tk = timing_begin(st);
         e = launch_self(T, W.bufs, A.cur, dd, st);
         timing_end(tk, "self", st);
@@ -332,7 +337,7 @@ mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, con
     e = launch_stage2(T, W.bufs, A, dd, st);
     timing_end(tk, "stage2", st);
     if (e != hipSuccess) return hip_status(e, "k_stage2 launch");
-    if (!stage2_needs_emit(T.M, dd)) return MMVM_OK;
+    if (!stage2_needs_emit(T.M, dd, W.bufs.N)) return MMVM_OK;
     tk = timing_begin(st);
     e = launch_emit(T, W.bufs, A, dd, st);
     timing_end(tk, "emit", st);
@@ -472,7 +477,8 @@ mmvm_status mmvm_sync(void* stream)
         int d = 0;
         if (hipMemcpy(&d, W->flag_ptr, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return MMVM_EDEVICE;
         f |= d;
-        if (d && hipMemset(W->flag_ptr, 0, sizeof(int)) != hipSuccess) return MMVM_EDEVICE;
+        if (d && (hipMemsetAsync(W->flag_ptr, 0, sizeof(int), st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+            return MMVM_EDEVICE;
     }
     if (f & 1) return MMVM_EZEROCIRC;
     if (f & 2) return MMVM_ENONFINITE;

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
 
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st)
 {
-    if (stage2_uses_mfma(T.M, dd)) return launch_self_pad(T, B, cur, st);
+    if (stage2_uses_mfma(T.M, dd, B.N)) return launch_self_pad(T, B, cur, st);
     const int threads = 256;
     dim3 grid((4 * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
@@ -523,7 +523,11 @@ __host__ __device__ inline int s2m_lds_doubles(int M)
     return a.total > b.total ? a.total : b.total;
 }
 
-bool stage2_uses_mfma(int M, bool dd) { return !dd && M > kMaxSmallOrder && M <= kS2MaxOrder; }
+bool mfma_order(int M) { return M >= kMinMfmaOrder && M <= kS2MaxOrder; }
+bool stage2_uses_mfma(int M, bool dd, int N)
+{
+    return !dd && mfma_order(M) && (M > kMaxSmallOrder || N == 1);
+}
 
 // ---------------------------------------------------------------------------
 // Large orders, FP64, on the matrix cores.  Same workgroup split as the
@@ -886,7 +890,7 @@ static size_t self_mfma_lds(int M)
     return sizeof(double) * (4 * (size_t)kSelfKS * ((sh.LP + 2) + (tz.TP + 2)) + (size_t)sh.LP * (tz.TP + 1));
 }
 
-bool stage2_fuses_emit(int M, bool dd, int N) { return stage2_uses_mfma(M, dd) && N == 1; }
+bool stage2_fuses_emit(int M, bool dd, int N) { return stage2_uses_mfma(M, dd, N) && N == 1; }
 
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st)
 {
@@ -1111,7 +1115,7 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
     if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
 }
 
-bool stage2_fuses_self(int M, bool dd) { return !dd && M <= kMaxSmallOrder; }
+bool stage2_fuses_self(int M, bool dd, int N) { return !dd && M <= kMaxSmallOrder && !stage2_uses_mfma(M, dd, N); }
 
 template <int M>
 static hipError_t launch_small(const DevTables& T, const StageBufs& B, const StageArgs& A, hipStream_t st)
@@ -1140,7 +1144,7 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
 
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {
-    if (stage2_fuses_self(T.M, use_dd)) {
+    if (stage2_fuses_self(T.M, use_dd, B.N)) {
         switch (T.M) {
         case 0: return launch_small<0>(T, B, A, st);
         case 1: return launch_small<1>(T, B, A, st);
@@ -1159,7 +1163,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     const int M1 = T.M + 1;
     dim3 grid(4 * M1, B.N);
     if (!use_dd) {
-        if (!stage2_uses_mfma(T.M, use_dd) || B.N != 1) return hipErrorInvalidValue;
+        if (!stage2_uses_mfma(T.M, use_dd, B.N) || B.N != 1) return hipErrorInvalidValue;
         const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
         if (shmem > 64 * 1024) {
             hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_mfma,
@@ -1193,7 +1197,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     return hipGetLastError();
 }
 
-bool stage2_needs_emit(int M, bool dd) { return !stage2_fuses_self(M, dd); }
+bool stage2_needs_emit(int M, bool dd, int N) { return !stage2_fuses_self(M, dd, N); }
 
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {

@@ -106,13 +106,13 @@ hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const Appl
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 // orders whose stage-2 kernel computes the self table itself
 constexpr int kMaxSmallOrder = 10;
-bool stage2_fuses_self(int M, bool dd);
+bool stage2_fuses_self(int M, bool dd, int N);
 // stage-2 contraction; at small orders also the drift and the RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,
                          hipStream_t st);
 // large orders: the contraction writes four partial sums per moment and a
 // second kernel adds them and applies the drift and the RK4 bookkeeping
-bool stage2_needs_emit(int M, bool dd);
+bool stage2_needs_emit(int M, bool dd, int N);
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd, hipStream_t st);
 
 // Matrix-core stage 2 (FP64, single vortex, orders kMaxSmallOrder + 1 .. kS2MaxOrder):
@@ -123,7 +123,10 @@ constexpr int kS2Threads = 512;
 constexpr int kS2Waves = kS2Threads / 64;
 constexpr int kS2MaxOrder = 47;
 constexpr int kS2TPad = 18;  // zero rows on either side of T
-bool stage2_uses_mfma(int M, bool dd);
+constexpr int kMinMfmaOrder = 7;  // a single vortex uses the matrix-core path from this order on
+// the order has matrix-core tables; the path runs for (M, precision, N)
+bool mfma_order(int M);
+bool stage2_uses_mfma(int M, bool dd, int N);
 
 struct S2Shape {
     int nrp, LP, RP, KA, KBP, LDS, LDY, LDT, NTR;

@@ -106,7 +106,7 @@ def structure(w, seed, amp=0.05):
 # ---------------------------------------------------------------------------
 # right-hand side, small cases covering several tiles, ragged tails and edges
 # ---------------------------------------------------------------------------
-CASES = [(1, 0), (1, 1), (1, 3), (1, 10), (2, 0), (2, 2), (3, 4), (5, 6), (67, 2), (130, 3)]
+CASES = [(1, 0), (1, 1), (1, 3), (1, 6), (1, 7), (1, 8), (1, 10), (2, 0), (2, 2), (3, 4), (5, 6), (67, 2), (130, 3)]
 
 
 @pytest.mark.parametrize("N,M", CASES)
@@ -227,7 +227,7 @@ def host_rk4_via_rhs(env, w, t0, nsteps, prec):
     return Y.cpu().numpy()
 
 
-@pytest.mark.parametrize("M,prec", [(12, 0), (17, 1), (24, 0), (40, 1), (40, 0)])
+@pytest.mark.parametrize("M,prec", [(7, 0), (10, 1), (12, 0), (17, 1), (24, 0), (40, 1), (40, 0)])
 def test_large_order_step_matches_rhs_driven_rk4(env, M, prec):
     """Single-vortex stepping at large orders (the matrix-core path finishes
     each stage inside the next stage's self kernel; the double-double path
