@@ -100,6 +100,27 @@ mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const 
 mmvm_status mmvm_step(const mmvm_problem* prob, double t0, double dt, int64_t nsteps, double* x,
                       double* mom, mmvm_precision prec, void* stream);
 
+/* A batch of independent single-vortex solves of one order (an ensemble, e.g. one
+ * initial condition at several Reynolds numbers): member j is the problem of one
+ * vortex with core lambda0[j] and viscosity nu[j] (HOST arrays [n]), and the
+ * members do not interact.  Stepping a batch gives, for every member, the result
+ * of stepping that vortex alone (same arithmetic), with one launch of each kernel
+ * for the whole batch.  Section: the single-particle moment equations,
+ * eq:moment_evolutionFinish; viscous core growth eq:phi00. */
+typedef struct {
+    int32_t n;             /* members, >= 1 */
+    int32_t order;         /* M, 0..MMVM_MAX_ORDER */
+    const double* nu;      /* [n] viscosity of each member, >= 0 */
+    const double* lambda0; /* [n] initial core scale of each member, > 0 */
+} mmvm_batch;
+
+/* nsteps classic RK4 steps of every member of the batch, in place on the DEVICE
+ * arrays x[n][2] (unchanged: a lone vortex does not move) and mom[n][K].
+ * Asynchronous, stream-ordered; errors as mmvm_step (MMVM_EORDER, MMVM_EINVAL;
+ * device-side checks latched for mmvm_sync). */
+mmvm_status mmvm_step_batch(const mmvm_batch* batch, double t0, double dt, int64_t nsteps, double* x,
+                            double* mom, mmvm_precision prec, void* stream);
+
 /* Waits for `stream` and returns (and clears) any error latched by device-side
  * checks of earlier calls on it: MMVM_EZEROCIRC or MMVM_ENONFINITE. */
 mmvm_status mmvm_sync(void* stream);

@@ -150,7 +150,7 @@ struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
         sselflo, spair, spad, ystate[2], accd, gpartd, gpart, total;
 };
-Layout layout_for(int N_, int M_, bool need_dd)
+Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 {
     const int K = (M_ + 1) * (M_ + 2) / 2;
     const int GM = M_ == 0 ? 1 : 2 * M_;
@@ -163,7 +163,7 @@ Layout layout_for(int N_, int M_, bool need_dd)
         return o;
     };
     L.flag = add(sizeof(int) * 16);  // first: fixed offset across layouts
-    L.lam0 = add(sizeof(double) * N_);
+    L.lam0 = add(sizeof(double) * 2 * N_);  // lambda_{j,0}^2 and nu_j
     L.xs = add(sizeof(double) * 2 * N_);
     L.ys = add(sizeof(double) * (size_t)N_ * K);
     L.accx = add(sizeof(double) * 2 * N_);
@@ -173,7 +173,7 @@ Layout layout_for(int N_, int M_, bool need_dd)
         L.alpha[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT[b] = add(sizeof(double) * (size_t)N_ * K);
         L.alphaT32[b] = add(sizeof(float) * (size_t)N_ * K);
-        const bool mx = stage2_uses_mfma(M_, false, N_);
+        const bool mx = stage2_uses_mfma(M_, false, solo);
         const S2Shape sh(M_, 0);
         L.alphaD[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LA() * sh.LP : 0);
         L.alphaS[b] = add(mx ? sizeof(double) * (size_t)N_ * sh.LP * sh.LP : 0);
@@ -181,9 +181,9 @@ Layout layout_for(int N_, int M_, bool need_dd)
     L.sself = add(sizeof(double) * (size_t)N_ * KG);
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
-    L.spad = add(stage2_uses_mfma(M_, false, N_) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
+    L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
-        const size_t dense = stage2_uses_mfma(M_, false, N_) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
+        const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
         for (int b = 0; b < 2; ++b) L.ystate[b] = add(dense);
         L.accd = add(dense);
         L.gpartd = add(4 * dense);
@@ -194,11 +194,11 @@ Layout layout_for(int N_, int M_, bool need_dd)
 }
 }  // namespace
 
-size_t Workspace::bytes_for(int N_, int M_, bool need_dd) { return layout_for(N_, M_, need_dd).total; }
+size_t Workspace::bytes_for(int N_, int M_, bool need_dd, bool solo) { return layout_for(N_, M_, need_dd, solo).total; }
 
-mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
+mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, bool solo, hipStream_t st)
 {
-    const Layout L = layout_for(N_, M_, need_dd);
+    const Layout L = layout_for(N_, M_, need_dd, solo);
     const size_t need = L.total;
     if (need > bytes) {
         // the old buffer may still be used by queued work on this stream
@@ -222,13 +222,15 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         // hipMemset runs on the null stream, which does not order work on
         // non-blocking streams
         if (hipMemsetAsync(base, 0, need, st) != hipSuccess) return MMVM_EDEVICE;
-        lam0_cache.clear();
+        par_cache.clear();
     }
     N = N_;
     M = M_;
     char* b = base;
     bufs.N = N_;
+    bufs.interact = (!solo && N_ > 1) ? 1 : 0;
     bufs.lam0sq = (const double*)(b + L.lam0);
+    bufs.nuv = (const double*)(b + L.lam0) + N_;
     bufs.xs = (double*)(b + L.xs);
     bufs.ys = (double*)(b + L.ys);
     bufs.accx = (double*)(b + L.accx);
@@ -238,7 +240,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
         bufs.alpha[q] = (double*)(b + L.alpha[q]);
         bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
         bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
-        const bool mx = stage2_uses_mfma(M_, false, N_);
+        const bool mx = stage2_uses_mfma(M_, false, solo);
         bufs.alphaD[q] = mx ? (double*)(b + L.alphaD[q]) : nullptr;
         bufs.alphaS[q] = mx ? (double*)(b + L.alphaS[q]) : nullptr;
     }
@@ -247,7 +249,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.s_pair = (double*)(b + L.spair);
     bufs.s_pad = (double*)(b + L.spad);
     {
-        const bool mx = stage2_uses_mfma(M_, false, N_);
+        const bool mx = stage2_uses_mfma(M_, false, solo);
         for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
         bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
         bufs.gpartD = mx ? (double*)(b + L.gpartd) : nullptr;
@@ -255,20 +257,23 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, hipStream_t st)
     bufs.gpart = (double*)(b + L.gpart);
     bufs.flag = (int*)(b + L.flag);
     flag_ptr = bufs.flag;
-    lam0_dev = (double*)(b + L.lam0);
+    par_dev = (double*)(b + L.lam0);
     return MMVM_OK;
 }
 
-mmvm_status Workspace::set_lambda0(const double* lambda0, int N_, hipStream_t st)
+mmvm_status Workspace::set_params(const double* lambda0, const double* nu, double nu0, int N_, hipStream_t st)
 {
-    std::vector<double> sq(N_);
-    for (int j = 0; j < N_; ++j) sq[j] = lambda0[j] * lambda0[j];
-    if (sq == lam0_cache) return MMVM_OK;
+    std::vector<double> p(2 * (size_t)N_);
+    for (int j = 0; j < N_; ++j) {
+        p[j] = lambda0[j] * lambda0[j];
+        p[N_ + j] = nu ? nu[j] : nu0;
+    }
+    if (p == par_cache) return MMVM_OK;
     // the device copy may be read by queued work; order the update on the stream
-    if (hipMemcpyAsync(lam0_dev, sq.data(), sizeof(double) * N_, hipMemcpyHostToDevice, st) != hipSuccess)
+    if (hipMemcpyAsync(par_dev, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, st) != hipSuccess)
         return MMVM_EDEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return MMVM_EDEVICE;
-    lam0_cache.swap(sq);
+    par_cache.swap(p);
     return MMVM_OK;
 }
 
@@ -316,12 +321,12 @@ static mmvm_status hip_status(hipError_t e, const char* where)
 // the kernels of one stage whose inputs are in buffer A.cur (prep already ran)
 mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st)
 {
-    const bool pair = W.bufs.N > 1;
+    const bool pair = W.bufs.interact != 0;
     const bool f32 = prec == MMVM_MIXED;
     const bool dd = use_dd(T.M, prec);
     hipError_t e;
     void* tk;
-    if (!stage2_fuses_self(T.M, dd, W.bufs.N)) {
+    if (!stage2_fuses_self(T.M, dd, !W.bufs.interact)) {
         tk = timing_begin(st);
         e = launch_self(T, W.bufs, A.cur, dd, st);
         timing_end(tk, "self", st);
@@ -337,7 +342,7 @@ mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, con
     e = launch_stage2(T, W.bufs, A, dd, st);
     timing_end(tk, "stage2", st);
     if (e != hipSuccess) return hip_status(e, "k_stage2 launch");
-    if (!stage2_needs_emit(T.M, dd, W.bufs.N)) return MMVM_OK;
+    if (!stage2_needs_emit(T.M, dd, !W.bufs.interact)) return MMVM_OK;
     tk = timing_begin(st);
     e = launch_emit(T, W.bufs, A, dd, st);
     timing_end(tk, "emit", st);
@@ -346,10 +351,10 @@ mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, con
 
 // stage inputs (xin, min_) at time t -> buffer `cur`
 mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
-                     double nu, mmvm_precision prec, hipStream_t st)
+                     mmvm_precision prec, hipStream_t st)
 {
     void* tk = timing_begin(st);
-    hipError_t e = launch_prep(T, W.bufs, cur, xin, min_, t, nu, W.bufs.N > 1, prec == MMVM_MIXED, st);
+    hipError_t e = launch_prep(T, W.bufs, cur, xin, min_, t, W.bufs.interact != 0, prec == MMVM_MIXED, st);
     timing_end(tk, "prep", st);
     return hip_status(e, "k_prep launch");
 }
@@ -430,18 +435,17 @@ mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const 
     Workspace* W = workspace_for(st);
     if (!W) return MMVM_EDEVICE;
     std::lock_guard<std::mutex> lk(W->mu);
-    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), st)) != MMVM_OK) return s;
-    if ((s = W->set_lambda0(prob->lambda0, prob->n, st)) != MMVM_OK) return s;
+    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), prob->n == 1, st)) != MMVM_OK) return s;
+    if ((s = W->set_params(prob->lambda0, nullptr, prob->nu, prob->n, st)) != MMVM_OK) return s;
     StageArgs A;
     std::memset(&A, 0, sizeof(A));
     A.mode = MODE_RHS;
     A.cur = 0;
     A.t_stage = t;
     A.t_next = t;
-    A.nu = prob->nu;
     A.dx = dx;
     A.dmom = dmom;
-    if ((s = run_prep(*T, *W, 0, x, mom, t, prob->nu, prec, st)) != MMVM_OK) return s;
+    if ((s = run_prep(*T, *W, 0, x, mom, t, prec, st)) != MMVM_OK) return s;
     return run_stage(*T, *W, prec, A, st);
 }
 
@@ -459,9 +463,34 @@ mmvm_status mmvm_step(const mmvm_problem* prob, double t0, double dt, int64_t ns
     Workspace* W = workspace_for(st);
     if (!W) return MMVM_EDEVICE;
     std::lock_guard<std::mutex> lk(W->mu);
-    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), st)) != MMVM_OK) return s;
-    if ((s = W->set_lambda0(prob->lambda0, prob->n, st)) != MMVM_OK) return s;
-    return run_steps(*T, *W, prob->nu, t0, dt, nsteps, x, mom, prec, st);
+    if ((s = W->ensure(prob->n, prob->order, use_dd(prob->order, prec), prob->n == 1, st)) != MMVM_OK) return s;
+    if ((s = W->set_params(prob->lambda0, nullptr, prob->nu, prob->n, st)) != MMVM_OK) return s;
+    return run_steps(*T, *W, t0, dt, nsteps, x, mom, prec, st);
+}
+
+mmvm_status mmvm_step_batch(const mmvm_batch* b, double t0, double dt, int64_t nsteps, double* x, double* mom,
+                            mmvm_precision prec, void* stream)
+{
+    if (!b) return MMVM_EINVAL;
+    if (b->n < 1 || b->order < 0 || b->order > MMVM_MAX_ORDER) return MMVM_EORDER;
+    if (!b->nu || !b->lambda0) return MMVM_EINVAL;
+    for (int j = 0; j < b->n; ++j) {
+        if (!(b->nu[j] >= 0.0) || !std::isfinite(b->nu[j])) return MMVM_EINVAL;
+        if (!(b->lambda0[j] > 0.0) || !std::isfinite(b->lambda0[j])) return MMVM_EINVAL;
+    }
+    if (!x || !mom || nsteps < 0 || !std::isfinite(t0) || !std::isfinite(dt)) return MMVM_EINVAL;
+    if (prec != MMVM_FP64 && prec != MMVM_MIXED) return MMVM_EINVAL;
+    if (nsteps == 0) return MMVM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables* T = nullptr;
+    mmvm_status s;
+    if ((s = device_tables(b->order, &T)) != MMVM_OK) return s;
+    Workspace* W = workspace_for(st);
+    if (!W) return MMVM_EDEVICE;
+    std::lock_guard<std::mutex> lk(W->mu);
+    if ((s = W->ensure(b->n, b->order, use_dd(b->order, prec), true, st)) != MMVM_OK) return s;
+    if ((s = W->set_params(b->lambda0, b->nu, 0.0, b->n, st)) != MMVM_OK) return s;
+    return run_steps(*T, *W, t0, dt, nsteps, x, mom, prec, st);
 }
 
 mmvm_status mmvm_sync(void* stream)

@@ -22,13 +22,15 @@ struct Workspace {
     int N = 0, M = 0;
     StageBufs bufs{};
     int* flag_ptr = nullptr;
-    double* lam0_dev = nullptr;
-    std::vector<double> lam0_cache;
+    double* par_dev = nullptr;       // [2N]: lambda_{j,0}^2, then the viscosity of each vortex
+    std::vector<double> par_cache;
     int latched = 0;
 
-    mmvm_status ensure(int N, int M, bool need_dd, hipStream_t st);
-    static size_t bytes_for(int N, int M, bool need_dd);
-    mmvm_status set_lambda0(const double* lambda0, int N, hipStream_t st);
+    // solo: the vortices do not interact (N = 1, or a batch of independent solves)
+    mmvm_status ensure(int N, int M, bool need_dd, bool solo, hipStream_t st);
+    static size_t bytes_for(int N, int M, bool need_dd, bool solo);
+    // lambda0 [N]; viscosity nu[N], or the scalar nu0 for every vortex when nu is null
+    mmvm_status set_params(const double* lambda0, const double* nu, double nu0, int N, hipStream_t st);
     void release();
     ~Workspace() { release(); }
 };
@@ -43,9 +45,9 @@ Workspace* workspace_for(hipStream_t st);
 mmvm_status validate(const mmvm_problem* prob);
 bool use_dd(int M, mmvm_precision prec);
 mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
-                     double nu, mmvm_precision prec, hipStream_t st);
+                     mmvm_precision prec, hipStream_t st);
 mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st);
-mmvm_status run_steps(const DevTables& T, Workspace& W, double nu, double t0, double dt, int64_t nsteps,
-                      double* x, double* mom, mmvm_precision prec, hipStream_t st);
+mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, int64_t nsteps, double* x,
+                      double* mom, mmvm_precision prec, hipStream_t st);
 
 }  // namespace mmvm

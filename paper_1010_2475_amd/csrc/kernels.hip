@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_alpha_dense_clear(StageBufs B, int M)
 
 __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N, int K, const double* __restrict__ xin,
                                               const double* __restrict__ min_, const double* __restrict__ lam0sq,
-                                              double t, double nu, double* __restrict__ xs, double* __restrict__ ys,
+                                              double t, double* __restrict__ xs, double* __restrict__ ys,
                                               double* __restrict__ lam2, double* __restrict__ alpha,
                                               double* __restrict__ alphaT, float* __restrict__ alphaT32,
                                               int* __restrict__ flag, int copy_state)
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
     const long total = (long)N * K;
     for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
         int j = (int)(idx / K), k = (int)(idx - (long)j * K);
-        double l2 = lam0sq[j] + 4.0 * nu * t;
+        double l2 = lam0sq[j] + 4.0 * B.nuv[j] * t;
         double mk = min_[idx];
         const int sk = shell_of(k);
         double a = mk * inv_lambda_pow(l2, sk);
@@ -88,20 +88,20 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
             double x0 = xin[2 * j], x1 = xin[2 * j + 1];
             xs[2 * j] = x0;
             xs[2 * j + 1] = x1;
-            if (N > 1 && mk == 0.0) atomicOr(flag, 1);
+            if (B.interact && mk == 0.0) atomicOr(flag, 1);
             if (!isfinite(x0) || !isfinite(x1)) atomicOr(flag, 2);
         }
     }
 }
 
 hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
-                       double t, double nu, bool need_pair, bool need_f32, hipStream_t st)
+                       double t, bool need_pair, bool need_f32, hipStream_t st)
 {
     long total = (long)B.N * T.K;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     bool copy = (min_ != B.ys);
-    launch_kernel(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, nu, B.xs,
+    launch_kernel(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, B.xs,
                        B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
                        need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
     if (B.alphaD[0]) {  // zeros of the dense layouts (disjoint from what k_prep writes)
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
 
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st)
 {
-    if (stage2_uses_mfma(T.M, dd, B.N)) return launch_self_pad(T, B, cur, st);
+    if (stage2_uses_mfma(T.M, dd, !B.interact)) return launch_self_pad(T, B, cur, st);
     const int threads = 256;
     dim3 grid((4 * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(512) void k_stage2_dd(DevTables T, StageBufs B, Sta
     }
     const double* ssh = B.s_self + (long)j * KG;
     const double* ssl = B.s_self_lo + (long)j * KG;
-    const double* sp = N > 1 ? B.s_pair + (long)j * KG : nullptr;
+    const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
     for (int g = tid; g < KG; g += nt) {
         R v = A::ld(ssh, ssl, g);
         if (sp) v = A::add(v, A::mk(sp[g]));
@@ -524,9 +524,9 @@ __host__ __device__ inline int s2m_lds_doubles(int M)
 }
 
 bool mfma_order(int M) { return M >= kMinMfmaOrder && M <= kS2MaxOrder; }
-bool stage2_uses_mfma(int M, bool dd, int N)
+bool stage2_uses_mfma(int M, bool dd, bool solo)
 {
-    return !dd && mfma_order(M) && (M > kMaxSmallOrder || N == 1);
+    return !dd && mfma_order(M) && (M > kMaxSmallOrder || solo);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,7 +551,7 @@ bool stage2_uses_mfma(int M, bool dd, int N)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBufs B, StageArgs S)
 {
-    const int M = T.M, K = T.K, GM = T.GM, M1 = M + 1;
+    const int M = T.M, GM = T.GM, M1 = M + 1;
     const int j = blockIdx.y;
     const int k2 = blockIdx.x >> 2, pass = (blockIdx.x >> 1) & 1, par = blockIdx.x & 1;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -565,85 +565,32 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     const int off2 = pass == 0 ? 1 : -1;
     const int imaxk = pass == 0 ? k2 : k2 - 1;
 
+    // Operands read straight from global memory (L2-resident, rows contiguous;
+    // every tile issues all its loads before its first product): the padded
+    // self-table rows of this parity, the banded factor operand of this (k2,
+    // pass), the signed moments and the padded binomials.  LDS holds only what
+    // the products pass to each other.
     extern __shared__ double smem[];
-    double* sS = smem + sh.r1;            // S rows [RP][LDS]              (A)
-    double* sW = sS + sh.RP * sh.LDS;     // W [KA][LP]                    (A)
-    double* sT = smem + sh.r1;            // T [NTR][LDT]                  (B -> C)
+    double* sT = smem + sh.t;             // T [NTR][LDT]                  (B -> C)
     double* sY = smem + sh.y;             // Y [RP][LDY]                   (A -> B)
-    double* sA2 = smem + sh.a2;           // signed alpha [LP][LP] (l2, l1) (B)
-    double* sU = smem + sh.y;             // U [nd][ni], over Y and alpha  (C -> last step)
-    double* sC = smem + sh.cb;            // C(l, i) [LP][LP]              (C); then partial sums
-    double* sG = smem + sh.gd;            // F'[k1][i][i] [M1][M1]         (last step)
-
-    // --- operands: contiguous copies, all loads of a thread issued first
-    constexpr int kS2Rows = 16 * ((kS2MaxOrder + 16) / 16);
-    constexpr int kSSlots = (kS2Rows * (4 * kS2KA + 1) / 2 + kS2Threads - 1) / kS2Threads;  // double2 of S
-    constexpr int kWSlots = (4 * kS2KA * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;         // double2 of W
-    constexpr int kCSlots = (kS2Rows * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;           // double2 of C
-    constexpr int kDSlots = ((kS2MaxOrder + 1) * (kS2MaxOrder + 1) + kS2Threads - 1) / kS2Threads;
-    constexpr int kASlots = (kS2Rows * kS2Rows / 2 + kS2Threads - 1) / kS2Threads;           // double2 of alpha
-    const double2* gS = reinterpret_cast<const double2*>(B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS);
-    const double2* gW = reinterpret_cast<const double2*>(T.wpad + ((long)k2 * 2 + pass) * KA * LP);
-    const double2* gC = reinterpret_cast<const double2*>(T.cpad);
-    const double2* gA = reinterpret_cast<const double2*>(B.alphaS[S.cur] + (long)j * LP * LP);
+    double* sU = smem + sh.y;             // U [nd][ni], over Y            (C -> last step)
+    double* sP = smem + sh.ps;            // partial sums of the last step [8][64]
+    const double* gS = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS;
+    const double* gW = T.wpad + ((long)k2 * 2 + pass) * KA * LP;
+    const double* gA = B.alphaS[S.cur] + (long)j * LP * LP;
     const double* gD = pass == 0 ? T.fd1 : T.fd0;
-    const int nS2 = sh.RP * sh.LDS / 2, nW2 = KA * LP / 2, nC2 = LP * LP / 2, nD = M1 * M1;
-    double2 vS[kSSlots], vW[kWSlots], vC[kCSlots], vA[kASlots];
-    double vD[kDSlots];
-#pragma unroll
-    for (int q = 0; q < kSSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        vS[q] = gS[e < nS2 ? e : 0];
-    }
-#pragma unroll
-    for (int q = 0; q < kWSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        vW[q] = gW[e < nW2 ? e : 0];
-    }
-#pragma unroll
-    for (int q = 0; q < kCSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        vC[q] = gC[e < nC2 ? e : 0];
-        vA[q] = gA[e < nC2 ? e : 0];
-    }
-#pragma unroll
-    for (int q = 0; q < kDSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        vD[q] = gD[e < nD ? e : 0];
-    }
-    double2* dS = reinterpret_cast<double2*>(sS);
-    double2* dW = reinterpret_cast<double2*>(sW);
-    double2* dC = reinterpret_cast<double2*>(sC);
-    double2* dA = reinterpret_cast<double2*>(sA2);
-#pragma unroll
-    for (int q = 0; q < kSSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        if (e < nS2) dS[e] = vS[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kWSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        if (e < nW2) dW[e] = vW[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kCSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        if (e < nC2) {
-            dC[e] = vC[q];
-            dA[e] = vA[q];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < kDSlots; ++q) {
-        const int e = tid + kS2Threads * q;
-        if (e < nD) sG[e] = vD[q];
-    }
-    __syncthreads();
 
+    // T is zero except the rows of this parity written after (B)
+    {
+        double2* dT = reinterpret_cast<double2*>(sT);
+        const double2 z2 = {0.0, 0.0};
+        for (int e = tid; e < sh.NTR * sh.LDT / 2; e += kS2Threads) dT[e] = z2;
+        if (tid == 0 && ((sh.NTR * sh.LDT) & 1)) sT[sh.NTR * sh.LDT - 1] = 0.0;
+    }
     const int tr = sh.RP >> 4, tc = LP >> 4;
     // (A)
     {
-        const View va = {sS, sh.LDS, 1}, vb = {sW, LP, 1};
+        const View va = {gS, sh.LDS, 1}, vb = {gW, LP, 1};
         for (int t = wave; t < tr * tc; t += kS2Waves) {
             const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
             // W[.][l2] is nonzero for g2 in [lo(l2), k2 + l2 + off2], lo = 1 + |l2 - k2| (pass 0),
@@ -660,14 +607,9 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
         }
     }
     __syncthreads();
-    // (B): the results stay in registers until every wavefront has read Y and
-    // the T area (over the operands of A) is cleared
+    // (B): the results stay in registers until every wavefront has read Y
     {
-        double2* dT = reinterpret_cast<double2*>(sT);
-        const double2 z2 = {0.0, 0.0};
-        for (int e = tid; e < sh.NTR * sh.LDT / 2; e += kS2Threads) dT[e] = z2;
-        if (tid == 0 && (sh.NTR * sh.LDT) & 1) sT[sh.NTR * sh.LDT - 1] = 0.0;
-        const View va = {sY, sh.LDY, 1}, vb = {sA2, LP, 1};
+        const View va = {sY, sh.LDY, 1}, vb = {gA, LP, 1};
         dbl4 dt[kS2TilesPerWave];
 #pragma unroll
         for (int q = 0; q < kS2TilesPerWave; ++q) {
@@ -678,7 +620,6 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
                 dt[q] = mfma_tile<kS2KB>(lane, (t / tc) * 16, c0, 0, s1, va, vb);
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int q = 0; q < kS2TilesPerWave; ++q) {
             const int t = wave + q * kS2Waves;
@@ -693,10 +634,10 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
         }
     }
     __syncthreads();
-    // (C) U = T(sheared) x C
+    // (C) U = T(sheared) x C; U overwrites Y, whose last reads preceded the barrier
     {
         const int td = (nd + 15) >> 4, ti = (ni + 15) >> 4;
-        const View va = {sT + (dlo + kS2TPad) * sh.LDT, sh.LDT, sh.LDT + 1}, vb = {sC, LP, 1};
+        const View va = {sT + (dlo + kS2TPad) * sh.LDT, sh.LDT, sh.LDT + 1}, vb = {T.cpad, LP, 1};
         for (int t = wave; t < td * ti; t += kS2Waves) {
             const int r0 = (t / ti) * 16, c0 = (t % ti) * 16;
             // l1 >= i >= c0 and 0 <= d + l1 <= GM
@@ -722,15 +663,15 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
             const int imax = pass == 0 ? k1 - 1 : k1;
             for (int i = wave; i <= imax; i += kS2Waves) {
                 const int d = pass == 0 ? k1 - 2 * i - 1 : k1 - 2 * i + 1;
-                v = fma(sG[k1 * M1 + i], sU[(d - dlo) * ni + i], v);
+                v = fma(gD[k1 * M1 + i], sU[(d - dlo) * ni + i], v);
             }
         }
-        sC[wave * 64 + lane] = v;
+        sP[wave * 64 + lane] = v;
     }
     __syncthreads();
     if (tid < nk1) {  // partial G[k1 = tid][k2] of this (pass, parity), dense layout
         double g = 0.0;
-        for (int w = 0; w < kS2Waves; ++w) g += sC[w * 64 + tid];
+        for (int w = 0; w < kS2Waves; ++w) g += sP[w * 64 + tid];
         B.gpartD[((long)j * 4 + (pass * 2 + par)) * LP * LP + tid * LP + k2] = pass == 0 ? -g : g;
     }
 }
@@ -804,9 +745,9 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         }
         __shared__ double pw[2][MMVM_MAX_ORDER + 1];  // lambda_prev^s / lambda_prev^2, lambda_next^{-s}
         if (tid <= M) {
-            const double lam2p = B.lam0sq[j] + 4.0 * P.nu * P.t_prev;
+            const double lam2p = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_prev;
             const double lamp = sqrt(lam2p);
-            const double lam2n = B.lam0sq[j] + 4.0 * P.nu * P.t_next;
+            const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_next;
             double lp = 1.0;
             for (int e = 0; e < tid; ++e) lp *= lamp;
             pw[0][tid] = lp / lam2p;
@@ -890,7 +831,7 @@ static size_t self_mfma_lds(int M)
     return sizeof(double) * (4 * (size_t)kSelfKS * ((sh.LP + 2) + (tz.TP + 2)) + (size_t)sh.LP * (tz.TP + 1));
 }
 
-bool stage2_fuses_emit(int M, bool dd, int N) { return stage2_uses_mfma(M, dd, N) && N == 1; }
+bool stage2_fuses_emit(int M, bool dd, bool solo) { return stage2_uses_mfma(M, dd, solo) && solo; }
 
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st)
 {
@@ -907,7 +848,7 @@ __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, 
     const int j = blockIdx.x, K = T.K;
     const int LP = 16 * ((T.M + 16) / 16);
     const long LL = (long)LP * LP;
-    const double lam2p = B.lam0sq[j] + 4.0 * P.nu * P.t_prev;
+    const double lam2p = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_prev;
     const double lamp = sqrt(lam2p);
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const int s = shell_of(k);
@@ -950,12 +891,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
     const int K = T.K, N = B.N, j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     __shared__ double red[2 * kEmitThreads / 64];
     const double* al = B.alpha[S.cur] + (long)j * K;
-    const double* sp = N > 1 ? B.s_pair + (long)j * T.KG : nullptr;
+    const double* sp = B.interact ? B.s_pair + (long)j * T.KG : nullptr;
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * S.nu * S.t_next;
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
     double xd1 = 0.0, xd2 = 0.0;
-    if (N > 1) centre_velocity(al, sp, K, lam, red, xd1, xd2);
+    if (B.interact) centre_velocity(al, sp, K, lam, red, xd1, xd2);
     const double* gj = B.gpart + (long)j * 4 * K * 2;
     const int LP = 16 * ((T.M + 16) / 16);
     for (int k = tid; k < K; k += nt) {
@@ -972,7 +913,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
         for (int e = 0; e < s; ++e) lp *= lam;
         lp /= lam2;
         double val = A::hi(A::madd(A::zero(), A::ld(T.c1_hi, T.c1_lo, k), g)) * lp;
-        if (N > 1) {  // drift, eq:last_termsimp: xdot_1 M_{k-e1} + xdot_2 M_{k-e2}
+        if (B.interact) {  // drift, eq:last_termsimp: xdot_1 M_{k-e1} + xdot_2 M_{k-e2}
             double lq = lp * lam;  // lambda^{s-1}
             if (k1 >= 1) val += xd1 * al[ctri(k1 - 1, kk2)] * lq;
             if (kk2 >= 1) val += xd2 * al[ctri(k1, kk2 - 1)] * lq;
@@ -1017,8 +958,8 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
     }
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * S.nu * S.t_next;
-    const double* sp = N > 1 ? B.s_pair + (long)j * KG : nullptr;
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
+    const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
     for (int i = tid; i < M1 * M1 * M1; i += nt) {
         sF0[i] = T.f0_hi[i];
         sF1[i] = T.f1_hi[i];
@@ -1040,7 +981,7 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
         sS[g] = acc;
     }
     double xd1 = 0.0, xd2 = 0.0;
-    if (N > 1) centre_velocity(sAl, sp, K, lam, red, xd1, xd2);
+    if (B.interact) centre_velocity(sAl, sp, K, lam, red, xd1, xd2);
     __syncthreads();
     // (A) second axis for every (pass, k2, g1, l2)
     for (int task = tid; task < NY; task += nt) {
@@ -1104,7 +1045,7 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
         for (int e = 0; e < s; ++e) lp *= lam;
         lp /= lam2;
         double val = T.c1_hi[k] * g * lp;
-        if (N > 1) {
+        if (B.interact) {
             const double lq = lp * lam;
             if (k1 >= 1) val += xd1 * sAl[ctri(k1 - 1, k2)] * lq;
             if (k2 >= 1) val += xd2 * sAl[ctri(k1, k2 - 1)] * lq;
@@ -1115,7 +1056,7 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
     if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
 }
 
-bool stage2_fuses_self(int M, bool dd, int N) { return !dd && M <= kMaxSmallOrder && !stage2_uses_mfma(M, dd, N); }
+bool stage2_fuses_self(int M, bool dd, bool solo) { return !dd && M <= kMaxSmallOrder && !stage2_uses_mfma(M, dd, solo); }
 
 template <int M>
 static hipError_t launch_small(const DevTables& T, const StageBufs& B, const StageArgs& A, hipStream_t st)
@@ -1144,7 +1085,7 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
 
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {
-    if (stage2_fuses_self(T.M, use_dd, B.N)) {
+    if (stage2_fuses_self(T.M, use_dd, !B.interact)) {
         switch (T.M) {
         case 0: return launch_small<0>(T, B, A, st);
         case 1: return launch_small<1>(T, B, A, st);
@@ -1163,7 +1104,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     const int M1 = T.M + 1;
     dim3 grid(4 * M1, B.N);
     if (!use_dd) {
-        if (!stage2_uses_mfma(T.M, use_dd, B.N) || B.N != 1) return hipErrorInvalidValue;
+        if (!stage2_uses_mfma(T.M, use_dd, !B.interact) || B.interact) return hipErrorInvalidValue;
         const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
         if (shmem > 64 * 1024) {
             hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_mfma,
@@ -1197,7 +1138,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     return hipGetLastError();
 }
 
-bool stage2_needs_emit(int M, bool dd, int N) { return !stage2_fuses_self(M, dd, N); }
+bool stage2_needs_emit(int M, bool dd, bool solo) { return !stage2_fuses_self(M, dd, solo); }
 
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)
 {

@@ -37,7 +37,9 @@ struct DevTables {
 // into buffer 1 - cur.
 struct StageBufs {
     int N;
+    int interact;          // the vortices interact (N > 1 and not a batch of independent solves)
     const double* lam0sq;  // [N] lambda_{j,0}^2
+    const double* nuv;     // [N] viscosity of the solve each vortex belongs to
     double* xs;            // [N][2] stage input positions
     double* ys;            // [N][K] stage input moments
     double* accx;          // [N][2] RK4 accumulators
@@ -71,7 +73,6 @@ struct StageArgs {
     double t_stage;    // time of this stage
     double t_next;     // time of the next stage (lambda of the next inputs)
     double dt;
-    double nu;
     // RK4 state (in place) / RHS outputs
     double* x;         // user positions  [N][2]
     double* mom;       // user moments    [N][K]
@@ -82,7 +83,7 @@ struct StageArgs {
 // prep: stage input (xin, min_) -> lam2[cur], alpha[cur], alphaT[cur]; checks
 // circulation/finiteness; copies the state into (xs, ys) when they differ
 hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
-                       double t, double nu, bool need_pair, bool need_f32, hipStream_t st);
+                       double t, bool need_pair, bool need_f32, hipStream_t st);
 // self velocity-derivative table (orders without a fused self term); dd = double-double
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st);
 
@@ -96,23 +97,23 @@ struct ApplyArgs {
     int ycur;          // ystate[ycur] holds y_n
     double t_prev;     // time of stage t
     double t_next;     // time of stage t + 1
-    double dt, nu;
+    double dt;
     double* mom_out;   // launch_apply_final: y_{n+1} -> the caller's moments
 };
-bool stage2_fuses_emit(int M, bool dd, int N);
+bool stage2_fuses_emit(int M, bool dd, bool solo);
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st);
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st);
 // pair velocity-derivative table (N > 1); f32 = mixed precision
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 // orders whose stage-2 kernel computes the self table itself
 constexpr int kMaxSmallOrder = 10;
-bool stage2_fuses_self(int M, bool dd, int N);
+bool stage2_fuses_self(int M, bool dd, bool solo);
 // stage-2 contraction; at small orders also the drift and the RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,
                          hipStream_t st);
 // large orders: the contraction writes four partial sums per moment and a
 // second kernel adds them and applies the drift and the RK4 bookkeeping
-bool stage2_needs_emit(int M, bool dd, int N);
+bool stage2_needs_emit(int M, bool dd, bool solo);
 hipError_t launch_emit(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd, hipStream_t st);
 
 // Matrix-core stage 2 (FP64, single vortex, orders kMaxSmallOrder + 1 .. kS2MaxOrder):
@@ -124,13 +125,14 @@ constexpr int kS2Waves = kS2Threads / 64;
 constexpr int kS2MaxOrder = 47;
 constexpr int kS2TPad = 18;  // zero rows on either side of T
 constexpr int kMinMfmaOrder = 7;  // a single vortex uses the matrix-core path from this order on
-// the order has matrix-core tables; the path runs for (M, precision, N)
+// the order has matrix-core tables; the path runs for (M, precision, solo), where
+// solo = the vortices do not interact (one vortex, or a batch of independent solves)
 bool mfma_order(int M);
-bool stage2_uses_mfma(int M, bool dd, int N);
+bool stage2_uses_mfma(int M, bool dd, bool solo);
 
 struct S2Shape {
     int nrp, LP, RP, KA, KBP, LDS, LDY, LDT, NTR;
-    int r1, y, a2, cb, gd, total;  // LDS region offsets and size (doubles, multiples of 4)
+    int t, y, ps, total;  // LDS regions of the stage-2 kernel (doubles, multiples of 4)
     __host__ __device__ S2Shape(int M, int par)
     {
         const int M1 = M + 1, GM = 2 * M;
@@ -139,18 +141,15 @@ struct S2Shape {
         RP = LP;                       // nrp <= M + 1 for either parity
         KA = 4 * ((GM >> 2) + 1);
         KBP = 4 * ((M >> 2) + 1);
-        LDS = KA + 1;                  // odd strides spread the rows over the LDS banks
-        LDY = LP + 1;
+        LDS = KA + 1;                  // row stride of the padded self table
+        LDY = LP + 1;                  // odd strides spread the rows over the LDS banks
         LDT = LP + 1;
         NTR = GM + 1 + 2 * kS2TPad;
-        const int a_ops = RP * LDS + KA * LP;   // S rows and W (first product)
-        const int t_ops = NTR * LDT;            // T, sheared-friendly (second -> third product)
-        r1 = 0;
-        y = up4(a_ops > t_ops ? a_ops : t_ops);
-        a2 = y + up4(RP * LDY);
-        cb = a2 + up4(LP * LP);
-        gd = cb + up4(LP * LP > kS2Waves * 64 ? LP * LP : kS2Waves * 64);
-        total = gd + up4(M1 * M1);
+        const int u = (2 * M + 1) * M1;  // U of the third product, at most
+        t = 0;                                        // T, sheared-friendly (second -> third product)
+        y = up4(NTR * LDT);                           // Y (first -> second product), then U
+        ps = y + up4(RP * LDY > u ? RP * LDY : u);    // partial sums of the last step
+        total = ps + up4(kS2Waves * 64);
     }
     __host__ __device__ static int up4(int n) { return (n + 3) & ~3; }
     // per-vortex size of the padded self table (both parities)

@@ -95,8 +95,8 @@ bool mmvm_server::admit_locked(Request* r)
     r->stream = (int)(r->ticket % kStreams);
     hipStream_t st = streams[r->stream];
     r->ws.reset(new Workspace());
-    mmvm_status s = r->ws->ensure(r->n, r->order, use_dd(r->order, r->prec), st);
-    if (s == MMVM_OK) s = r->ws->set_lambda0(r->lambda0.data(), r->n, st);
+    mmvm_status s = r->ws->ensure(r->n, r->order, use_dd(r->order, r->prec), r->n == 1, st);
+    if (s == MMVM_OK) s = r->ws->set_params(r->lambda0.data(), nullptr, r->nu, r->n, st);
     const size_t sb = state_bytes(r->n, r->order);
     if (s == MMVM_OK && hipMalloc((void**)&r->dx, sb) != hipSuccess) s = MMVM_ENOMEM;
     if (s == MMVM_OK) {
@@ -171,7 +171,7 @@ void mmvm_server::run()
             hipStream_t st = streams[r->stream];
             if (r->done_steps == 0 && r->stats.t_start == 0.0) r->stats.t_start = now();
             if (s == MMVM_OK)
-                s = run_steps(*T, *r->ws, r->nu, r->t0 + (double)r->done_steps * r->dt, r->dt, c, r->dx, r->dmom,
+                s = run_steps(*T, *r->ws, r->t0 + (double)r->done_steps * r->dt, r->dt, c, r->dx, r->dmom,
                               r->prec, st);
             if (s == MMVM_OK && hipEventRecord(r->ev, st) != hipSuccess) s = MMVM_EDEVICE;
             if (s != MMVM_OK) {
@@ -257,7 +257,7 @@ mmvm_status mmvm_submit(mmvm_server* srv, const mmvm_problem* prob, double t0, d
     r->lambda0.assign(prob->lambda0, prob->lambda0 + n);
     r->x.assign(x0, x0 + 2 * (size_t)n);
     r->mom.assign(mom0, mom0 + (size_t)n * K);
-    r->footprint = state_bytes(n, M) + Workspace::bytes_for(n, M, use_dd(M, prec));
+    r->footprint = state_bytes(n, M) + Workspace::bytes_for(n, M, use_dd(M, prec), n == 1);
     if (r->footprint > srv->budget) return MMVM_EBUDGET;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return MMVM_EINVAL;

@@ -17,7 +17,6 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
     StageArgs A = A0;
     ApplyArgs P{};
     P.dt = A.dt;
-    P.nu = A.nu;
     int cur = 0;
     hipError_t e = hipSuccess;
     for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
@@ -64,23 +63,22 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
     return MMVM_OK;
 }
 
-mmvm_status run_steps(const DevTables& T, Workspace& W, double nu, double t0, double dt, int64_t nsteps,
-                      double* x, double* mom, mmvm_precision prec, hipStream_t st)
+mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, int64_t nsteps, double* x,
+                      double* mom, mmvm_precision prec, hipStream_t st)
 {
     static const double cst[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
     StageArgs A;
     std::memset(&A, 0, sizeof(A));
     A.mode = MODE_RK4;
     A.dt = dt;
-    A.nu = nu;
     A.x = x;
     A.mom = mom;
-    A.want_pair = W.bufs.N > 1;
+    A.want_pair = W.bufs.interact != 0;
     A.want_f32 = prec == MMVM_MIXED;
     int cur = 0;
-    mmvm_status r = run_prep(T, W, cur, x, mom, t0, nu, prec, st);
+    mmvm_status r = run_prep(T, W, cur, x, mom, t0, prec, st);
     if (r != MMVM_OK) return r;
-    if (stage2_fuses_emit(T.M, use_dd(T.M, prec), W.bufs.N)) return run_steps_fused(T, W, A, t0, nsteps, st);
+    if (stage2_fuses_emit(T.M, use_dd(T.M, prec), !W.bufs.interact)) return run_steps_fused(T, W, A, t0, nsteps, st);
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int s = 0; s < 4; ++s) {
             A.stage = s;

@@ -37,6 +37,11 @@ class Problem(ctypes.Structure):
                 ("lambda0", ctypes.POINTER(ctypes.c_double))]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("order", ctypes.c_int32), ("nu", ctypes.POINTER(ctypes.c_double)),
+                ("lambda0", ctypes.POINTER(ctypes.c_double))]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("steps", ctypes.c_int64)]
@@ -44,7 +49,7 @@ class Stats(ctypes.Structure):
 
 _lib = None
 
-SYMBOLS = ["mmvm_coeffs", "mmvm_rhs", "mmvm_step", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
+SYMBOLS = ["mmvm_coeffs", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
            "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
            "mmvm_status_string"]
 
@@ -61,6 +66,8 @@ def lib():
     L.mmvm_coeffs.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mmvm_rhs.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
     L.mmvm_step.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
+    L.mmvm_step_batch.argtypes = [ctypes.POINTER(Batch), ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp,
+                                  ctypes.c_int, vp]
     L.mmvm_sync.argtypes = [vp]
     L.mmvm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
     L.mmvm_submit.argtypes = [vp, pp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, dp, dp, ctypes.c_int,
@@ -136,6 +143,17 @@ def step(M, nu, lambda0, t0, dt, nsteps, x, mom, prec=FP64, stream=None):
     N, K = p.n, K_of(M)
     _check(lib().mmvm_step(ctypes.byref(p), float(t0), float(dt), int(nsteps), _dev(x, (N, 2), "x"),
                            _dev(mom, (N, K), "mom"), int(prec), _stream(stream)), "mmvm_step")
+
+
+def step_batch(M, nu, lambda0, t0, dt, nsteps, x, mom, prec=FP64, stream=None):
+    """Steps a batch of independent single-vortex solves (mmvm_step_batch)."""
+    lam = np.ascontiguousarray(np.atleast_1d(lambda0), dtype=np.float64)
+    nuv = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(np.asarray(nu, dtype=np.float64)), lam.shape))
+    dp = ctypes.POINTER(ctypes.c_double)
+    b = Batch(len(lam), int(M), nuv.ctypes.data_as(dp), lam.ctypes.data_as(dp))
+    N, K = len(lam), K_of(M)
+    _check(lib().mmvm_step_batch(ctypes.byref(b), float(t0), float(dt), int(nsteps), _dev(x, (N, 2), "x"),
+                                 _dev(mom, (N, K), "mom"), int(prec), _stream(stream)), "mmvm_step_batch")
 
 
 def sync(stream=None):

@@ -64,6 +64,21 @@ def test_argument_validation_without_device(mm):
     # multi-vortex above the compiled pair orders
     p = mm.Problem(2, 7, 0.01, dp)
     assert L.mmvm_rhs(ctypes.byref(p), 0.0, vp(8), vp(8), vp(8), vp(8), 0, None) == -3
+    # batches: null, empty, order out of range, bad member parameters, null state
+    nu = np.array([0.01, 0.02])
+    nup = nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.mmvm_step_batch(None, 0.0, 1e-3, 1, vp(8), vp(8), 0, None) == -1
+    b = mm.Batch(0, 5, nup, dp)
+    assert L.mmvm_step_batch(ctypes.byref(b), 0.0, 1e-3, 1, vp(8), vp(8), 0, None) == -3
+    b = mm.Batch(2, 41, nup, dp)
+    assert L.mmvm_step_batch(ctypes.byref(b), 0.0, 1e-3, 1, vp(8), vp(8), 0, None) == -3
+    negnu = np.array([0.01, -1.0])
+    b = mm.Batch(2, 5, negnu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dp)
+    assert L.mmvm_step_batch(ctypes.byref(b), 0.0, 1e-3, 1, vp(8), vp(8), 0, None) == -1
+    b = mm.Batch(1, 5, nup, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert L.mmvm_step_batch(ctypes.byref(b), 0.0, 1e-3, 1, vp(8), vp(8), 0, None) == -1
+    b = mm.Batch(2, 5, nup, dp)
+    assert L.mmvm_step_batch(ctypes.byref(b), 0.0, 1e-3, 1, None, vp(8), 0, None) == -1
     # unknown table kind, too small buffer
     assert L.mmvm_coeffs(4, 7, None, 0, None) == -1
     buf = np.zeros(4)

@@ -255,6 +255,29 @@ def test_large_order_step_matches_oracle(env, orc):
         assert np.all(x_g == w.x)
 
 
+@pytest.mark.parametrize("M,prec", [(5, 1), (10, 0), (24, 0), (33, 0), (40, 1)])
+def test_batch_matches_individual_solves(env, M, prec):
+    """A batch of independent single-vortex solves (different viscosities and
+    cores) gives every member exactly the result of stepping it alone."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    members = [wl.single_random(M=M, Re=Re, seed=s, lam0=l0) for Re, s, l0 in ((100.0, 2, 2.0), (1e3, 3, 1.5),
+                                                                                  (1e4, 4, 1.0))]
+    for w in members:
+        w.dt = 2e-3
+    dev = torch.device("cuda:0")
+    X = torch.tensor(np.concatenate([w.x for w in members]), device=dev)
+    Mo = torch.tensor(np.concatenate([w.mom for w in members]), device=dev)
+    print("step_batch M=%d prec=%d" % (M, prec), flush=True)
+    mm.step_batch(M, [w.nu for w in members], [w.lam0[0] for w in members], 0.05, 2e-3, 7, X, Mo, prec)
+    mm.sync()
+    got = Mo.cpu().numpy()
+    for i, w in enumerate(members):
+        _, m1 = gpu_step(env, w, 0.05, 7, prec)
+        assert np.array_equal(got[i], m1[0]), (i, np.abs(got[i] - m1[0]).max())
+    assert np.array_equal(X.cpu().numpy(), np.concatenate([w.x for w in members]))
+
+
 # ---------------------------------------------------------------------------
 # the workloads at full size (sampled outputs the oracle computes one by one)
 # ---------------------------------------------------------------------------
