@@ -75,6 +75,8 @@ mmvm_status device_tables(int M, const DevTables** out)
     d.binom = upload(*o, H.binom, err);
     d.fd0 = upload(*o, H.fd0, err);
     d.fd1 = upload(*o, H.fd1, err);
+    d.fd0_lo = upload(*o, H.fd0_lo, err);
+    d.fd1_lo = upload(*o, H.fd1_lo, err);
     {
         // zero-padded operands of the matrix-core stage 2 (see S2Shape)
         std::vector<double> wpad, cpad;

@@ -927,88 +927,163 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
 // ---------------------------------------------------------------------------
 // stage 2 for small orders (M <= kMaxSmallOrder): one workgroup per vortex
 // computes its self table, then all k2 and both halves of the contraction at
-// once (four barriers per stage), then the drift and the RK4 update.
+// once (four barriers per stage), then the drift and the RK4 update.  The same
+// stage body drives the persistent kernel k_solo_rk4 below.
 // ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B, StageArgs S)
+// the first l1 whose rows l2 <= M - l1 no longer fit in half the work of step B
+constexpr int small_split(int M)
 {
-    constexpr int K = (M + 1) * (M + 2) / 2;
-    constexpr int GM = M == 0 ? 1 : 2 * M;
-    constexpr int KG = (GM + 1) * (GM + 2) / 2;
-    constexpr int M1 = M + 1;
-    constexpr int NY = 2 * M1 * KG;  // (pass, k2, g1, l2)
-    extern __shared__ double smem[];
-    double* sAl = smem;        // [K] alpha
-    double* sA = sAl + K;      // [K] (-1)^{|l|} alpha
-    double* sS = sA + K;       // [KG] S_self + S_pair
-    double* sY = sS + KG;      // [NY]
-    double* sT = sY + NY;      // [NY]
-    double* sP = sT + NY;      // [2][K][M1] partials of step C
-    double* sF0 = sP + 2 * K * M1;      // [M1^3] factor table f0
-    double* sF1 = sF0 + M1 * M1 * M1;   // [M1^3] factor table f1
-    double* sT0 = sF1 + M1 * M1 * M1;   // [tri(T0N)] Psi0 table
-    __shared__ double red[32];
+    const int M1 = M + 1, K = M1 * (M1 + 1) / 2;
+    int w = 0, L = 0;
+    while (L < M1 && 2 * (w + (M1 - L)) <= K) w += M1 - L++;
+    return L < 1 ? 1 : L;
+}
 
-    const int N = B.N, j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    const double* al = B.alpha[S.cur] + (long)j * K;
-    for (int l = tid; l < K; l += nt) {
-        const double a = al[l];
-        sAl[l] = a;
-        sA[l] = (shell_of(l) & 1) ? -a : a;
-    }
-    const double lam2 = B.lam2[S.cur][j];
-    const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
-    const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
+template <int M>
+struct SmallShape {
+    static constexpr int K = (M + 1) * (M + 2) / 2;
+    static constexpr int GM = M == 0 ? 1 : 2 * M;
+    static constexpr int KG = (GM + 1) * (GM + 2) / 2;
+    static constexpr int M1 = M + 1;
+    static constexpr int G1 = GM + 1;         // rows g1 of the velocity-derivative table
+    static constexpr int G2 = GM + 2;         // its columns g2 = 0 .. GM + 1 (zero beyond the triangle)
+    static constexpr int NY = 2 * M1 * G1 * M1;  // (pass, k2, g1, l2)
+    static constexpr int T0N = ((M == 0 ? 1 : 3 * M) + 1) / 2 + 1;
+    static constexpr int NT0 = (T0N + 1) * (T0N + 2) / 2;
+    static constexpr int T0W = T0N + 1;       // row length of the rectangular Psi0 table
+    // LDS regions (doubles); the rectangular layouts hold zeros outside their triangles
+    static constexpr int AL = 0;                     // [K] alpha, shell-major
+    static constexpr int AU = AL + K;                // [M1][M1] alpha at (l1, l2)
+    static constexpr int AR = AU + M1 * M1;          // [M1][M1] (-1)^{|l|} alpha at (l1, l2)
+    static constexpr int SS = AR + M1 * M1;          // [G1][G2] S_self + S_pair
+    static constexpr int SY = SS + G1 * G2;          // [NY] step A output
+    static constexpr int ST = SY + NY;               // [NY] step B output
+    static constexpr int SP = ST + NY;               // [2][K][M1] partials of step C
+    static constexpr int F0 = SP + 2 * K * M1;       // [M1^3] factor table f0
+    static constexpr int F1 = F0 + M1 * M1 * M1;     // [M1^3] factor table f1
+    static constexpr int T0 = F1 + M1 * M1 * M1;     // [T0W][T0W] Psi0 table
+    static constexpr int TOTAL = T0 + T0W * T0W;
+    // step B: a thread owns l1 < LB or l1 >= LB of one row (about half the work each)
+    static constexpr int LB = small_split(M);
+};
+
+// The tables of the small-order stage into LDS, and the zeros of the
+// rectangular layouts (entries outside the triangles are never written later).
+template <int M>
+__device__ __forceinline__ void small_load_tables(const DevTables& T, double* smem)
+{
+    typedef SmallShape<M> Sh;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    constexpr int M1 = Sh::M1;
     for (int i = tid; i < M1 * M1 * M1; i += nt) {
-        sF0[i] = T.f0_hi[i];
-        sF1[i] = T.f1_hi[i];
+        smem[Sh::F0 + i] = T.f0_hi[i];
+        smem[Sh::F1 + i] = T.f1_hi[i];
     }
-    const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
-    for (int i = tid; i < nt0; i += nt) sT0[i] = T.t0_hi[i];
-    __syncthreads();
-    // self table S_self[g] = sum_m alpha_m Psi0(m + g) (c = 2), plus the pair table
-    for (int g = tid; g < KG; g += nt) {
-        double acc = 0.0;
-        if (g > 0) {
-            const int gs = shell_of(g);
-            const int g2 = g - gs * (gs + 1) / 2, g1 = gs - g2;
-            for (int m2 = g2 & 1; m2 <= M; m2 += 2)
-                for (int m1 = g1 & 1; m1 + m2 <= M; m1 += 2)
-                    acc = fma(sAl[ctri(m1, m2)], sT0[ctri((m1 + g1) >> 1, (m2 + g2) >> 1)], acc);
-            if (sp) acc += sp[g];
+    for (int i = tid; i < Sh::T0W * Sh::T0W; i += nt) {
+        const int a = i / Sh::T0W, b = i - a * Sh::T0W;
+        smem[Sh::T0 + i] = a + b <= Sh::T0N ? T.t0_hi[ctri(a, b)] : 0.0;
+    }
+    for (int i = tid; i < M1 * M1; i += nt) {
+        const int l1 = i / M1, l2 = i - l1 * M1;
+        if (l1 + l2 > M) {
+            smem[Sh::AU + i] = 0.0;
+            smem[Sh::AR + i] = 0.0;
         }
-        sS[g] = acc;
     }
-    double xd1 = 0.0, xd2 = 0.0;
-    if (B.interact) centre_velocity(sAl, sp, K, lam, red, xd1, xd2);
+    for (int i = tid; i < Sh::G1 * Sh::G2; i += nt) {
+        const int g1 = i / Sh::G2, g2 = i - g1 * Sh::G2;
+        if (g1 + g2 > Sh::GM) smem[Sh::SS + i] = 0.0;
+    }
+}
+
+// the scaled moment alpha_k (k = (k1, k2), shell s) into the three layouts
+template <int M>
+__device__ __forceinline__ void small_put_alpha(double* smem, int k, int s, int k1, int k2, double a)
+{
+    typedef SmallShape<M> Sh;
+    smem[Sh::AL + k] = a;
+    smem[Sh::AU + k1 * Sh::M1 + k2] = a;
+    smem[Sh::AR + k1 * Sh::M1 + k2] = (s & 1) ? -a : a;
+}
+
+// Self table, steps A, B and C of one stage; alpha is in LDS (a barrier after
+// it was written), sp = the pair table or null.  Ends with a barrier; the
+// partial sums of step C are in the SP region.
+template <int M>
+__device__ __forceinline__ void small_stage(double* smem, const double* sp)
+{
+    typedef SmallShape<M> Sh;
+    constexpr int K = Sh::K, GM = Sh::GM, KG = Sh::KG, M1 = Sh::M1, G1 = Sh::G1, G2 = Sh::G2, NY = Sh::NY;
+    constexpr int T0W = Sh::T0W, LB = Sh::LB;
+    const double* sAU = smem + Sh::AU;
+    const double* sAR = smem + Sh::AR;
+    double* sS = smem + Sh::SS;
+    double* sY = smem + Sh::SY;
+    double* sT = smem + Sh::ST;
+    double* sP = smem + Sh::SP;
+    const double* sF0 = smem + Sh::F0;
+    const double* sF1 = smem + Sh::F1;
+    const double* sT0 = smem + Sh::T0;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // self table S[g1][g2] = sum_m alpha_m Psi0(m + g) (c = 2), plus the pair
+    // table; four lanes share one g, each taking every fourth m2 of its parity
+    for (int task = tid; task < 4 * KG; task += nt) {
+        const int g = task >> 2, q = task & 3;
+        const int gs = shell_of(g);
+        const int g2 = g - gs * (gs + 1) / 2, g1 = gs - g2;
+        double acc = 0.0;
+        for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) {
+            const double* a = sAU + (g1 & 1) * M1 + m2;
+            const double* p = sT0 + ((g1 + (g1 & 1)) >> 1) * T0W + ((m2 + g2) >> 1);
+            for (int m1 = g1 & 1; m1 + m2 <= M; m1 += 2, a += 2 * M1, p += T0W) acc = fma(*a, *p, acc);
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (q == 0) sS[g1 * G2 + g2] = g == 0 ? 0.0 : (sp ? acc + sp[g] : acc);
+    }
     __syncthreads();
-    // (A) second axis for every (pass, k2, g1, l2)
+    // (A) second axis: Y[pass][k2][g1][l2] = sum_i f[k2][l2][i] S[g1][k2 + l2 - 2i +- 1]
+    // (lanes over g1; zeros of S cover g1 + g2 > GM)
     for (int task = tid; task < NY; task += nt) {
-        const int pass = task / (M1 * KG);
-        const int r = task - pass * (M1 * KG);
-        const int k2 = r / KG, q = r - k2 * KG;
-        const int g1 = q / M1, l2 = q - g1 * M1;
+        const int c = task / G1, g1 = task - c * G1;  // c = (pass, k2, l2)
+        const int pass = c / (M1 * M1);
+        const int r = c - pass * (M1 * M1);
+        const int k2 = r / M1, l2 = r - k2 * M1;
         const double* f = (pass == 0 ? sF0 : sF1) + (k2 * M1 + l2) * M1;
         const int imax = pass == 0 ? (l2 < k2 ? l2 : k2) : (l2 < k2 - 1 ? l2 : k2 - 1);
-        const int off = pass == 0 ? 1 : -1;
+        const double* srow = sS + g1 * G2 + k2 + l2 + (pass == 0 ? 1 : -1);
         double acc = 0.0;
-        for (int i = 0; i <= imax; ++i) {
-            const int g2 = k2 + l2 - 2 * i + off;
-            const int gg = g1 + g2;
-            if (gg > GM || gg == 0) continue;
-            acc = fma(f[i], sS[ctri(g1, g2)], acc);
-        }
-        sY[task] = acc;
+        for (int i = 0; i <= imax; ++i) acc = fma(f[i], srow[-2 * i], acc);
+        sY[((pass * M1 + k2) * G1 + g1) * M1 + l2] = acc;
     }
     __syncthreads();
-    // (B) l2 against the moments for every (pass, k2, g1, l1)
-    for (int task = tid; task < NY; task += nt) {
-        const int base = task - task % M1;  // (pass, k2, g1) row start
-        const int l1 = task - base;
-        double acc = 0.0;
-        for (int l2 = 0; l2 <= M - l1; ++l2) acc = fma(sA[ctri(l1, l2)], sY[base + l2], acc);
-        sT[task] = acc;
+    // (B) T[row][l1] = sum_{l2 <= M - l1} (-1)^{|l|} alpha_l Y[row][l2]: the row
+    // in registers, a thread per (row, l1 < LB) or (row, l1 >= LB)
+    constexpr int NR = 2 * M1 * G1;
+    for (int task = tid; task < 2 * NR; task += nt) {
+        const int half = task / NR, row = task - half * NR;
+        double y[M1];
+        const double* yr = sY + row * M1;
+#pragma unroll
+        for (int l2 = 0; l2 < M1; ++l2) y[l2] = yr[l2];
+        double* tr = sT + row * M1;
+        if (half == 0) {
+#pragma unroll
+            for (int l1 = 0; l1 < LB; ++l1) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 <= M - l1; ++l2) acc = fma(sAR[l1 * M1 + l2], y[l2], acc);
+                tr[l1] = acc;
+            }
+        } else {
+#pragma unroll
+            for (int l1 = LB; l1 < M1; ++l1) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 <= M - l1; ++l2) acc = fma(sAR[l1 * M1 + l2], y[l2], acc);
+                tr[l1] = acc;
+            }
+        }
     }
     __syncthreads();
     // (C) first axis for every (pass, k, l1)
@@ -1018,42 +1093,145 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
         const int k = r / M1, l1 = r - k * M1;
         const int ks = shell_of(k);
         const int k2 = k - ks * (ks + 1) / 2, k1 = ks - k2;
-        const double* tcol = sT + (long)(pass * M1 + k2) * KG + l1;
+        const double* tcol = sT + (long)(pass * M1 + k2) * G1 * M1 + l1;
         double acc = 0.0;
         if (pass == 0) {
             const double* f = sF1 + (k1 * M1 + l1) * M1;
             const int imax = l1 < k1 - 1 ? l1 : k1 - 1;
-            for (int i = 0; i <= imax; ++i) acc = fma(f[i], tcol[(k1 + l1 - 2 * i - 1) * M1], acc);
+            const double* tp = tcol + (k1 + l1 - 1) * M1;
+            for (int i = 0; i <= imax; ++i, tp -= 2 * M1) acc = fma(f[i], *tp, acc);
             acc = -acc;
         } else {
             const double* f = sF0 + (k1 * M1 + l1) * M1;
             const int imax = l1 < k1 ? l1 : k1;
-            for (int i = 0; i <= imax; ++i) {
-                const int g1 = k1 + l1 - 2 * i + 1;
-                if (g1 <= GM) acc = fma(f[i], tcol[g1 * M1], acc);
-            }
+            const int i0 = k1 + l1 + 1 > GM ? 1 : 0;  // g1 = k1 + l1 - 2i + 1 <= GM
+            const double* tp = tcol + (k1 + l1 + 1 - 2 * i0) * M1;
+            for (int i = i0; i <= imax; ++i, tp -= 2 * M1) acc = fma(f[i], *tp, acc);
         }
         sP[task] = acc;
     }
     __syncthreads();
+}
+
+// dM_k/dt from the partial sums of step C: lambda^{|k|-2} c1_k G_k, plus the
+// drift xdot_1 M_{k-e1} + xdot_2 M_{k-e2} when the vortex moves; dM_00 = 0.
+template <int M>
+__device__ __forceinline__ double small_value(const DevTables& T, const double* smem, int k, double lam, double lam2,
+                                              bool drift, double xd1, double xd2)
+{
+    typedef SmallShape<M> Sh;
+    constexpr int K = Sh::K, M1 = Sh::M1;
+    const double* sP = smem + Sh::SP;
+    const double* sAl = smem + Sh::AL;
+    double g = 0.0;
+    for (int l1 = 0; l1 < M1; ++l1) g += sP[k * M1 + l1] + sP[(K + k) * M1 + l1];
+    const int s = shell_of(k);
+    const int k2 = k - s * (s + 1) / 2, k1 = s - k2;
+    double lp = 1.0;
+    for (int e = 0; e < s; ++e) lp *= lam;
+    lp /= lam2;
+    double val = T.c1_hi[k] * g * lp;
+    if (drift) {
+        const double lq = lp * lam;
+        if (k1 >= 1) val += xd1 * sAl[ctri(k1 - 1, k2)] * lq;
+        if (k2 >= 1) val += xd2 * sAl[ctri(k1, k2 - 1)] * lq;
+    }
+    if (k == 0) val = 0.0;
+    return val;
+}
+
+template <int M>
+__global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B, StageArgs S)
+{
+    typedef SmallShape<M> Sh;
+    constexpr int K = Sh::K, KG = Sh::KG;
+    extern __shared__ double smem[];
+    __shared__ double red[32];
+    const double* sAl = smem + Sh::AL;
+
+    const int j = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const double* al = B.alpha[S.cur] + (long)j * K;
+    for (int l = tid; l < K; l += nt) {
+        const int s = shell_of(l), l2 = l - s * (s + 1) / 2;
+        small_put_alpha<M>(smem, l, s, s - l2, l2, al[l]);
+    }
+    const double lam2 = B.lam2[S.cur][j];
+    const double lam = sqrt(lam2);
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
+    const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
+    small_load_tables<M>(T, smem);
+    __syncthreads();
+    double xd1 = 0.0, xd2 = 0.0;
+    if (B.interact) centre_velocity(sAl, sp, K, lam, red, xd1, xd2);
+    small_stage<M>(smem, sp);
     for (int k = tid; k < K; k += nt) {
-        double g = 0.0;
-        for (int l1 = 0; l1 < M1; ++l1) g += sP[k * M1 + l1] + sP[(K + k) * M1 + l1];
-        const int s = shell_of(k);
-        const int k2 = k - s * (s + 1) / 2, k1 = s - k2;
-        double lp = 1.0;
-        for (int e = 0; e < s; ++e) lp *= lam;
-        lp /= lam2;
-        double val = T.c1_hi[k] * g * lp;
-        if (B.interact) {
-            const double lq = lp * lam;
-            if (k1 >= 1) val += xd1 * sAl[ctri(k1 - 1, k2)] * lq;
-            if (k2 >= 1) val += xd2 * sAl[ctri(k1, k2 - 1)] * lq;
-        }
-        if (k == 0) val = 0.0;
-        emit_moment(B, S, T.M, j, k, s, K, val, lam2n);
+        const double val = small_value<M>(T, smem, k, lam, lam2, B.interact != 0, xd1, xd2);
+        emit_moment(B, S, T.M, j, k, shell_of(k), K, val, lam2n);
     }
     if (tid == 0) emit_position(B, S, j, xd1, xd2, lam2n);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent RK4 for independent single vortices of small order: workgroup j
+// advances solve j through all nsteps classic RK4 steps (four stages each)
+// without leaving the kernel.  The tables stay in LDS for the whole run; the
+// state y_n and the RK4 accumulator of moment k live in the registers of
+// thread k.  A single vortex does not move (its pair table and drift are
+// zero), so the centre is not touched.  Each stage is the arithmetic of
+// k_prep + k_stage2_small at the same stage times, so the two routes agree
+// bit for bit.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(1024) void k_solo_rk4(DevTables T, const double* __restrict__ lam0sq,
+                                                   const double* __restrict__ nuv, double t0, double dt,
+                                                   int64_t nsteps, double* __restrict__ mom, int* __restrict__ flag)
+{
+    typedef SmallShape<M> Sh;
+    constexpr int K = Sh::K;
+    static_assert(K <= 1024, "one thread per moment");
+    extern __shared__ double smem[];
+    const int j = blockIdx.x, tid = threadIdx.x;
+    const double l0 = lam0sq[j], nu = nuv[j];
+    double* my = mom + (long)j * K;
+    const bool owner = tid < K;
+    const int sk = owner ? shell_of(tid) : 0;
+    const int k2 = owner ? tid - sk * (sk + 1) / 2 : 0, k1 = sk - k2;
+    double yn = 0.0, acc = 0.0, ys = 0.0;
+    if (owner) {
+        yn = my[tid];
+        ys = yn;
+        if (!isfinite(yn)) atomicOr(flag, 2);
+    }
+    small_load_tables<M>(T, smem);
+    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    const double wts[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    for (int64_t n = 0; n < nsteps; ++n) {
+        for (int s = 0; s < 4; ++s) {
+            const double ts = t0 + ((double)n + cst[s]) * dt;
+            const double lam2 = l0 + 4.0 * nu * ts;
+            if (owner) small_put_alpha<M>(smem, tid, sk, k1, k2, ys * inv_lambda_pow(lam2, sk));
+            __syncthreads();
+            small_stage<M>(smem, nullptr);
+            if (owner) {
+                const double val = small_value<M>(T, smem, tid, sqrt(lam2), lam2, false, 0.0, 0.0);
+                // the RK4 bookkeeping of rk4_update, in registers
+                if (s == 0) acc = wts[0] * val;
+                else if (s < 3) acc += wts[s] * val;
+                if (s < 3) {
+                    ys = yn + cst[s + 1] * dt * val;
+                } else {
+                    yn = yn + dt * (acc + wts[3] * val);
+                    ys = yn;
+                }
+            }
+            // the next writes of alpha follow the last reads of this stage
+            // (steps A-C) across the barrier that ends small_stage
+        }
+    }
+    if (owner) {
+        my[tid] = yn;
+        if (!isfinite(yn)) atomicOr(flag, 2);
+    }
 }
 
 bool stage2_fuses_self(int M, bool dd, bool solo) { return !dd && M <= kMaxSmallOrder && !stage2_uses_mfma(M, dd, solo); }
@@ -1061,15 +1239,11 @@ bool stage2_fuses_self(int M, bool dd, bool solo) { return !dd && M <= kMaxSmall
 template <int M>
 static hipError_t launch_small(const DevTables& T, const StageBufs& B, const StageArgs& A, hipStream_t st)
 {
-    constexpr int K = (M + 1) * (M + 2) / 2;
-    constexpr int GM = M == 0 ? 1 : 2 * M;
-    constexpr int KG = (GM + 1) * (GM + 2) / 2;
-    constexpr int M1 = M + 1;
-    const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
-    const size_t shmem = sizeof(double) * (2 * K + KG + 4 * (size_t)M1 * KG + 2 * (size_t)K * M1 +
-                                           2 * (size_t)M1 * M1 * M1 + (size_t)nt0);
+    typedef SmallShape<M> Sh;
+    if (T.T0N != Sh::T0N) return hipErrorInvalidValue;
+    const size_t shmem = sizeof(double) * (size_t)Sh::TOTAL;
     // few vortices: wide workgroups for latency; many: one to four wavefronts each
-    int threads = B.N <= 32 ? 1024 : (2 * M1 * KG >= 1024 ? 256 : (2 * M1 * KG >= 256 ? 128 : 64));
+    int threads = B.N <= 32 ? 1024 : (Sh::NY >= 1024 ? 256 : (Sh::NY >= 256 ? 128 : 64));
     if (shmem > 64 * 1024) {
         hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_small<M>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
@@ -1081,6 +1255,49 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
     }
     launch_kernel(k_stage2_small<M>, dim3(B.N), dim3(threads), shmem, st, T, B, A);
     return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_solo_M(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0,
+                                double dt, int64_t nsteps, double* mom, int* flag, hipStream_t st)
+{
+    typedef SmallShape<M> Sh;
+    if (T.T0N != Sh::T0N) return hipErrorInvalidValue;
+    const size_t shmem = sizeof(double) * (size_t)Sh::TOTAL;
+    if (shmem > 64 * 1024) {
+        hipError_t ea = hipFuncSetAttribute((const void*)k_solo_rk4<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)shmem);
+        if (ea != hipSuccess) {
+            (void)hipGetLastError();
+            report_hip_error(ea, "hipFuncSetAttribute(k_solo_rk4 dynamic LDS)");
+            return ea;
+        }
+    }
+    const int threads = Sh::K > 256 ? 1024 : kSoloThreads;
+    launch_kernel(k_solo_rk4<M>, dim3(nb), dim3(threads), shmem, st, T, lam0sq, nuv, t0, dt, nsteps, mom, flag);
+    return hipGetLastError();
+}
+
+bool solo_persistent(int M, bool dd) { return !dd && M >= 0 && M <= kMaxSoloOrder; }
+
+hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0, double dt,
+                           int64_t nsteps, double* mom, int* flag, hipStream_t st)
+{
+    switch (T.M) {
+    case 0: return launch_solo_M<0>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 1: return launch_solo_M<1>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 2: return launch_solo_M<2>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 3: return launch_solo_M<3>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 4: return launch_solo_M<4>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 5: return launch_solo_M<5>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 6: return launch_solo_M<6>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 7: return launch_solo_M<7>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 8: return launch_solo_M<8>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 9: return launch_solo_M<9>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 10: return launch_solo_M<10>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 11: return launch_solo_M<11>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool use_dd, hipStream_t st)

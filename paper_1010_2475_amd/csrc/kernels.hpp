@@ -19,6 +19,8 @@ struct DevTables {
     const double* binom;   // [M+1][M+1] C(l, i)
     const double* fd0;     // [M+1][M+1] f0[k][i][i]
     const double* fd1;     // [M+1][M+1] f1[k][i][i]
+    const double* fd0_lo;  // low parts of fd0, fd1 (double-double)
+    const double* fd1_lo;
     const double* wpad;    // matrix-core stage 2: banded factor operand [M+1][2][KA][LP] (k2, pass, g2, l2)
     const double* cpad;    // matrix-core stage 2: C(l, i) zero-padded [LP][LP]
     const double* t0d;     // matrix-core self table: Psi0 dense [T0R][TP] (a, b), zero beyond a + b <= T0N
@@ -107,6 +109,13 @@ hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const Appl
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 // orders whose stage-2 kernel computes the self table itself
 constexpr int kMaxSmallOrder = 10;
+// Persistent RK4 of independent single vortices (one workgroup per solve, all
+// steps in one launch) for orders 0..kMaxSoloOrder, FP64 arithmetic.
+constexpr int kMaxSoloOrder = 11;
+constexpr int kSoloThreads = 1024;
+bool solo_persistent(int M, bool dd);
+hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0, double dt,
+                           int64_t nsteps, double* mom, int* flag, hipStream_t st);
 bool stage2_fuses_self(int M, bool dd, bool solo);
 // stage-2 contraction; at small orders also the drift and the RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,

@@ -95,10 +95,15 @@ void build(Tables& T, int M)
 
     T.fd0.assign((size_t)M1 * M1, 0.0);
     T.fd1.assign((size_t)M1 * M1, 0.0);
+    T.fd0_lo.assign((size_t)M1 * M1, 0.0);
+    T.fd1_lo.assign((size_t)M1 * M1, 0.0);
     for (int k = 0; k <= M; ++k)
         for (int i = 0; i <= M; ++i) {
-            T.fd0[(size_t)k * M1 + i] = T.f0_hi[((size_t)k * M1 + i) * M1 + i];
-            T.fd1[(size_t)k * M1 + i] = T.f1_hi[((size_t)k * M1 + i) * M1 + i];
+            const size_t o = ((size_t)k * M1 + i) * M1 + i;
+            T.fd0[(size_t)k * M1 + i] = T.f0_hi[o];
+            T.fd1[(size_t)k * M1 + i] = T.f1_hi[o];
+            T.fd0_lo[(size_t)k * M1 + i] = T.f0_lo[o];
+            T.fd1_lo[(size_t)k * M1 + i] = T.f1_lo[o];
         }
 
     // --- projection constants at lambda = 1

@@ -38,7 +38,7 @@ struct Tables {
     std::vector<double> binom;
     // diagonals of the factor tables, [M+1][M+1] (k, i): fd0[k][i] = f0[k][i][i] = 2^i k!/(k-i)!,
     // fd1[k][i] = f1[k][i][i] = 2^{i+1} k!/(k-i-1)!, so that f[k][l][i] = C(l, i) fd[k][i]
-    std::vector<double> fd0, fd1;
+    std::vector<double> fd0, fd1, fd0_lo, fd1_lo;
     // c1[k] = (-1)^{|k|} / (2^{|k|} k1! k2!)  (the projection constant at lambda = 1), hi/lo
     std::vector<double> c1_hi, c1_lo;
     // Edge coefficients of the pair kernel for shells n = 2..P:

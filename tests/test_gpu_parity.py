@@ -242,6 +242,65 @@ def test_large_order_step_matches_rhs_driven_rk4(env, M, prec):
     assert m_g[0, 0] == w.mom[0, 0]
 
 
+@pytest.mark.parametrize("M,prec", [(0, 0), (1, 1), (3, 0), (6, 1), (9, 0), (10, 0), (11, 1)])
+def test_persistent_step_matches_rhs_driven_rk4(env, M, prec):
+    """Small orders: one workgroup runs every RK4 stage of a single vortex
+    without leaving the kernel; it must agree with RK4 assembled on the host
+    from one mmvm_rhs per stage."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=M, Re=500.0)
+    w.dt = 2e-3
+    x_g, m_g = gpu_step(env, w, 0.05, 5, prec)
+    m_h = host_rk4_via_rhs(env, w, 0.05, 5, prec)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * (0.05 + 5 * w.dt))
+    assert normwise(M, lam_t, m_h, m_g) <= 1e-13
+    assert m_g[0, 0] == w.mom[0, 0]
+    assert np.all(x_g == w.x)
+
+
+@pytest.mark.parametrize("M,steps,dt", [(4, 30, 5e-3), (11, 6, 1e-2)])
+def test_persistent_step_matches_oracle(env, orc, M, steps, dt):
+    """The persistent kernel against the oracle's RK4 over a stretch long
+    enough for the core to spread (Re 100)."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=M, Re=100.0, seed=9)
+    w.dt = dt
+    x_r, m_r = orc.rk4(w.M, w.nu, w.lam0, 0.0, w.dt, steps, w.x, w.mom)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * steps * w.dt)
+    x_g, m_g = gpu_step(env, w, 0.0, steps, 0)
+    assert normwise(w.M, lam_t, m_r, m_g) <= FP64_TOL
+    assert np.all(x_g == w.x)
+
+
+def test_persistent_batch_of_many_uneven_solves(env, orc):
+    """300 independent order-8 solves in one launch (more workgroups than
+    compute units), with different viscosities, cores and moments: sampled
+    members against the oracle, and every member against stepping it alone."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    rng = np.random.default_rng(21)
+    nb, M, steps, dt = 300, 8, 6, 3e-3
+    members = []
+    for b in range(nb):
+        w = wl.single_random(M=M, Re=float(10 ** rng.uniform(2, 4)), seed=100 + b, lam0=float(rng.uniform(0.8, 2.5)))
+        w.dt = dt
+        members.append(w)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(np.concatenate([w.x for w in members]), device=dev)
+    Mo = torch.tensor(np.concatenate([w.mom for w in members]), device=dev)
+    print("step_batch nb=%d M=%d" % (nb, M), flush=True)
+    mm.step_batch(M, [w.nu for w in members], [w.lam0[0] for w in members], 0.0, dt, steps, X, Mo, 0)
+    mm.sync()
+    got = Mo.cpu().numpy()
+    for i in (0, 1, 137, 255, 256, 299):
+        w = members[i]
+        _, m_r = orc.rk4(w.M, w.nu, w.lam0, 0.0, dt, steps, w.x, w.mom)
+        lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * steps * dt)
+        assert normwise(M, lam_t, m_r, got[i:i + 1]) <= FP64_TOL, i
+        _, m1 = gpu_step(env, w, 0.0, steps, 0)
+        assert np.array_equal(got[i], m1[0]), i
+
+
 def test_large_order_step_matches_oracle(env, orc):
     """Order 12, two RK4 steps of one vortex against the oracle's RK4."""
     from paper_1010_2475_amd import workloads as wl
@@ -255,7 +314,7 @@ def test_large_order_step_matches_oracle(env, orc):
         assert np.all(x_g == w.x)
 
 
-@pytest.mark.parametrize("M,prec", [(5, 1), (10, 0), (24, 0), (33, 0), (40, 1)])
+@pytest.mark.parametrize("M,prec", [(5, 1), (10, 0), (11, 0), (12, 1), (24, 0), (33, 0), (40, 1)])
 def test_batch_matches_individual_solves(env, M, prec):
     """A batch of independent single-vortex solves (different viscosities and
     cores) gives every member exactly the result of stepping it alone."""
