@@ -175,6 +175,49 @@ __device__ __forceinline__ void emit_position(const StageBufs& B, const StageArg
 // ---------------------------------------------------------------------------
 hipError_t launch_self_pad(const DevTables& T, const StageBufs& B, int cur, hipStream_t st);
 
+// Compensated accumulation (Ogita, Rump and Oishi's Dot2, extended to
+// double-double operands): the running sum s carries a second word c that
+// collects the exact rounding error of every product (TwoProd) and of every
+// addition (TwoSum), plus the cross terms of the low words.  The result s + c
+// is as accurate as a sum computed in twice the working precision, at about
+// twelve operations per multiply-add (a double-double multiply-add costs
+// about twenty-eight).
+struct Acc2 {
+    double s, c;
+};
+
+// acc += (xh + xl)(yh + yl), the xl yl term dropped
+__device__ __forceinline__ void dot2(Acc2& a, double xh, double xl, double yh, double yl)
+{
+#pragma clang fp contract(off)
+    const double p = xh * yh;
+    double t = fma(xh, yh, -p);
+    t = fma(xl, yh, t);
+    t = fma(xh, yl, t);
+    const double s = a.s + p;
+    const double bb = s - a.s;
+    const double es = (a.s - (s - bb)) + (p - bb);
+    a.s = s;
+    a.c += es + t;
+}
+
+// acc += x (yh + yl)
+__device__ __forceinline__ void dot2(Acc2& a, double x, double yh, double yl)
+{
+#pragma clang fp contract(off)
+    const double p = x * yh;
+    double t = fma(x, yh, -p);
+    t = fma(x, yl, t);
+    const double s = a.s + p;
+    const double bb = s - a.s;
+    const double es = (a.s - (s - bb)) + (p - bb);
+    a.s = s;
+    a.c += es + t;
+}
+
+// the accumulated value as a normalised double-double
+__device__ __forceinline__ dd acc2_value(const Acc2& a) { return two_sum(a.s, a.c); }
+
 template <bool DD>
 __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int KG, int T0N,
                                               const double* __restrict__ alpha, const double* __restrict__ t0h,
@@ -196,8 +239,10 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
         if (DD) tl[i] = t0l[i];
     }
     __syncthreads();
+    // four lanes share one entry g (eight for the compensated sums)
+    constexpr int LANES = DD ? 8 : 4;
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = gt >> 2, q = gt & 3;
+    const int g = gt / LANES, q = gt % LANES;
     const bool live = g < KG && g > 0;
     int g1 = 0, g2 = 0;
     if (live) {
@@ -217,22 +262,26 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
         acc += __shfl_xor(acc, 2, 64);
         if (q == 0 && g < KG) sself[(long)j * KG + g] = live ? acc : 0.0;
     } else {
-        dd acc = dd_make(0.0);
+        // compensated accumulation of alpha_m (Psi0_hi + Psi0_lo)
+        Acc2 acc{0.0, 0.0};
         if (live)
-            for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) {
+            for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 2 * LANES) {
                 const int b2 = (m2 + g2) >> 1;
                 for (int m1 = g1 & 1; m1 + m2 <= M; m1 += 2) {
                     const int ti = ctri((m1 + g1) >> 1, b2);
-                    acc = dd_add(acc, dd_mul(dd_make(th[ti], tl[ti]), dd_make(sa[ctri(m1, m2)])));
+                    dot2(acc, sa[ctri(m1, m2)], th[ti], tl[ti]);
                 }
             }
-        for (int off = 1; off <= 2; off <<= 1) {
-            dd o = dd_make(__shfl_xor(acc.hi, off, 64), __shfl_xor(acc.lo, off, 64));
-            acc = dd_add(acc, o);
+        for (int off = 1; off < LANES; off <<= 1) {
+            const double os = __shfl_xor(acc.s, off, 64), oc = __shfl_xor(acc.c, off, 64);
+            const dd t = two_sum(acc.s, os);
+            acc.s = t.hi;
+            acc.c += oc + t.lo;
         }
         if (q == 0 && g < KG) {
-            sself[(long)j * KG + g] = live ? acc.hi : 0.0;
-            sself_lo[(long)j * KG + g] = live ? acc.lo : 0.0;
+            const dd v = acc2_value(acc);
+            sself[(long)j * KG + g] = live ? v.hi : 0.0;
+            sself_lo[(long)j * KG + g] = live ? v.lo : 0.0;
         }
     }
 }
@@ -241,7 +290,7 @@ hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd,
 {
     if (stage2_uses_mfma(T.M, dd, !B.interact)) return launch_self_pad(T, B, cur, st);
     const int threads = 256;
-    dim3 grid((4 * T.KG + threads - 1) / threads, B.N);
+    dim3 grid(((dd ? 8 : 4) * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
     size_t shmem = sizeof(double) * ((size_t)T.K + (dd ? 2 : 1) * (size_t)nt0);
     if (dd)
@@ -341,130 +390,192 @@ __device__ void centre_velocity(const double* al, const double* sp, int K, doubl
     xd2 = p2 / (gam * lam);
 }
 
-// Large orders, double-double (the FP64 path above the double-double
-// threshold).  blockIdx.x = (k2, pass, par): pass 0 = Y half (f0 on the second
-// axis, f1 on the first, minus sign), pass 1 = X half; par = parity of the rows
-// g1 this workgroup owns (step C of (k1, l1) reads rows of parity k1+l1+1 only).
+// ---------------------------------------------------------------------------
+// Large orders on the strict FP64 path (above the double-double threshold).
+// The contraction's alternating sums cancel, so every sum is accumulated in a
+// compensated form (Acc2 / dot2 above), with double-double operands and
+// results.
+// ---------------------------------------------------------------------------
+// LDS layout of the double-double stage 2 (doubles; double-double values as
+// (hi, lo) pairs).  Rows r of the velocity-derivative table hold g1 = par + 2r
+// with g2 = 0 .. GM - g1 (row-packed); step B overwrites it with T.
+struct DDShape {
+    int M1, nrp;
+    int s, f, y, ar, bin, fd, total;
+    __host__ __device__ DDShape(int M, int par)
+    {
+        M1 = M + 1;
+        nrp = (2 * M - par) / 2 + 1;
+        const int m2 = M1 * M1;
+        s = 0;                      // S, then T: nrp * M1 <= M1^2 pairs
+        f = s + 2 * m2;             // f[k2][l2][i] of the second axis: [M1][M1] pairs
+        y = f + 2 * m2;             // Y, then the partials of step C: [M1][M1] pairs
+        ar = y + 2 * m2;            // (-1)^{|l|} alpha at (l1, l2), zero beyond the triangle: [M1 + 1][M1]
+        bin = ar + (M1 + 1) * M1;   // C(l, i): [M1][M1]
+        fd = bin + m2;              // f[k1][i][i] of the first axis: [M1][M1] pairs
+        total = fd + 2 * m2;
+    }
+    // start of row r (in pairs): rows have GM - par - 2r + 1 entries
+    __host__ __device__ static int row_off(int M, int par, int r) { return r * (2 * M - par + 1) - r * (r - 1); }
+};
+
+constexpr int kDDThreads = 1024;
+
+// blockIdx.x = (k2, pass, par): pass 0 = Y half (f0 on the second axis, f1 on
+// the first, minus sign), pass 1 = X half; par = parity of the rows g1 this
+// workgroup owns (step C of (k1, l1) reads rows of parity k1 + l1 + 1 only).
 // Each workgroup writes its partial sum over l1 for every k1 of its k2; the
-// emit kernel adds the four partials.
-template <bool FSLICE>
-__global__ __launch_bounds__(512) void k_stage2_dd(DevTables T, StageBufs B, StageArgs S)
+// emit kernel adds the four partials.  Single vortices only (the interacting
+// path stops far below the double-double orders).
+__global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs B, StageArgs S)
 {
-    typedef ArithDD A;
-    typedef typename A::T R;
-    const int M = T.M, K = T.K, GM = T.GM, KG = T.KG, M1 = M + 1;
-    const int N = B.N;
+    const int M = T.M, K = T.K, GM = T.GM, M1 = M + 1;
     const int j = blockIdx.y;
     const int k2 = blockIdx.x >> 2, pass = (blockIdx.x >> 1) & 1, par = blockIdx.x & 1;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int rows = GM + 1;  // rows * M1 == KG
-    const int nrp = (rows - par + 1) / 2;  // rows of this parity
-
-    // LDS: sA [K] signed alpha; R1 [KG] S (step A) then T (steps B, C);
-    //      R2 [KG] Y (step A -> B); sG [M1*M1] partial per (k1, l1); sF [M1*M1] factor slice
+    const DDShape L(M, par);
+    const int nrp = L.nrp;
     extern __shared__ double smem[];
-    R* sA = reinterpret_cast<R*>(smem);
-    R* R1 = sA + K;
-    R* R2 = R1 + KG;
-    R* sG = R2 + KG;
-    R* sF = sG + M1 * M1;
+    double* sS = smem + L.s;
+    double* sF = smem + L.f;
+    double* sY = smem + L.y;
+    double* sAR = smem + L.ar;
+    double* sBin = smem + L.bin;
+    double* sFd = smem + L.fd;
 
-    const double* al = B.alpha[S.cur] + (long)j * K;
-    for (int l = tid; l < K; l += nt) {
-        int s = shell_of(l);
-        sA[l] = A::mk((s & 1) ? -al[l] : al[l]);
-    }
-    const double* ssh = B.s_self + (long)j * KG;
-    const double* ssl = B.s_self_lo + (long)j * KG;
-    const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
-    for (int g = tid; g < KG; g += nt) {
-        R v = A::ld(ssh, ssl, g);
-        if (sp) v = A::add(v, A::mk(sp[g]));
-        R1[g] = v;
-    }
-    const double* fh = pass == 0 ? T.f0_hi : T.f1_hi;
-    const double* fl = pass == 0 ? T.f0_lo : T.f1_lo;
-    const long fbase = (long)k2 * M1 * M1;
-    if (FSLICE)
-        for (int i = tid; i < M1 * M1; i += nt) sF[i] = A::ld(fh + fbase, fl + fbase, i);
-    __syncthreads();
-    // (A) second axis on the rows of parity par
-    for (int task = tid; task < nrp * M1; task += nt) {
-        const int rr = task / M1, l2 = task - rr * M1;
-        const int g1 = par + 2 * rr;
-        R acc = A::zero();
-        const int imax = pass == 0 ? (l2 < k2 ? l2 : k2) : (l2 < k2 - 1 ? l2 : k2 - 1);
-        const int off = pass == 0 ? 1 : -1;
-        for (int i = 0; i <= imax; ++i) {
-            const int g2 = k2 + l2 - 2 * i + off;
-            const int gg = g1 + g2;
-            if (gg > GM || gg == 0) continue;
-            const R f = FSLICE ? sF[l2 * M1 + i] : A::ld(fh + fbase, fl + fbase, l2 * M1 + i);
-            acc = A::madd(acc, f, R1[ctri(g1, g2)]);
-        }
-        R2[g1 * M1 + l2] = acc;
-    }
-    __syncthreads();
-    // (B) T[g1][l1] = sum_{l2 <= M - l1} sA[l1, l2] Y[g1][l2], register-blocked 4 x 4
+    // fills: S rows of parity par, the second-axis factor slice, signed alpha,
+    // binomials and the first-axis diagonals
     {
-        const int nbg = (nrp + 3) / 4, nbl = (M1 + 3) / 4;
-        for (int blk = tid; blk < nbg * nbl; blk += nt) {
-            const int bg = blk / nbl, bl = blk - bg * nbl;
-            const int r0 = bg * 4, l0 = bl * 4;
-            R acc[4][4];
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] = A::zero();
-            const int l2max = M - l0;
-            for (int l2 = 0; l2 <= l2max; ++l2) {
-                R y[4], a4[4];
-                for (int u = 0; u < 4; ++u)
-                    y[u] = (r0 + u < nrp) ? R2[(par + 2 * (r0 + u)) * M1 + l2] : A::zero();
-                for (int v = 0; v < 4; ++v) {
-                    const int l1 = l0 + v;
-                    a4[v] = (l1 <= M && l1 + l2 <= M) ? sA[ctri(l1, l2)] : A::zero();
-                }
-                for (int u = 0; u < 4; ++u)
-                    for (int v = 0; v < 4; ++v) acc[u][v] = A::madd(acc[u][v], a4[v], y[u]);
+        const double* ssh = B.s_self + (long)j * T.KG;
+        const double* ssl = B.s_self_lo + (long)j * T.KG;
+        for (int e = tid; e < nrp * (GM + 1); e += nt) {
+            const int r = e / (GM + 1), g2 = e - r * (GM + 1);
+            const int g1 = par + 2 * r;
+            if (g1 + g2 > GM) continue;
+            const int g = ctri(g1, g2), o = DDShape::row_off(M, par, r) + g2;
+            const bool z = g == 0;
+            sS[2 * o] = z ? 0.0 : ssh[g];
+            sS[2 * o + 1] = z ? 0.0 : ssl[g];
+        }
+        const double* fh = (pass == 0 ? T.f0_hi : T.f1_hi) + (long)k2 * M1 * M1;
+        const double* fl = (pass == 0 ? T.f0_lo : T.f1_lo) + (long)k2 * M1 * M1;
+        for (int e = tid; e < M1 * M1; e += nt) {
+            sF[2 * e] = fh[e];
+            sF[2 * e + 1] = fl[e];
+        }
+        const double* al = B.alpha[S.cur] + (long)j * K;
+        for (int e = tid; e < (M1 + 1) * M1; e += nt) {
+            const int l1 = e / M1, l2 = e - l1 * M1;
+            double a = 0.0;
+            if (l1 + l2 <= M) {
+                a = al[ctri(l1, l2)];
+                if ((l1 + l2) & 1) a = -a;
             }
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v)
-                    if (r0 + u < nrp && l0 + v <= M) R1[(par + 2 * (r0 + u)) * M1 + l0 + v] = acc[u][v];
+            sAR[e] = a;
+        }
+        const double* dh = pass == 0 ? T.fd1 : T.fd0;
+        const double* dl = pass == 0 ? T.fd1_lo : T.fd0_lo;
+        for (int e = tid; e < M1 * M1; e += nt) {
+            sBin[e] = T.binom[e];
+            sFd[2 * e] = dh[e];
+            sFd[2 * e + 1] = dl[e];
         }
     }
     __syncthreads();
-    // (C) first axis for the (k1, l1) whose rows have parity par
-    const int nk1 = M - k2 + 1;
-    for (int task = tid; task < nk1 * M1; task += nt) {
-        const int k1 = task / M1, l1 = task - k1 * M1;
-        R acc = A::zero();
-        if (((k1 + l1 + 1) & 1) == par) {
-            const long fo = ((long)k1 * M1 + l1) * M1;
-            if (pass == 0) {
-                // - sum_i f1[k1][l1][i] T[k1+l1-2i-1][l1]
-                const int imax = l1 < k1 - 1 ? l1 : k1 - 1;
-                for (int i = 0; i <= imax; ++i)
-                    acc = A::madd(acc, A::ld(T.f1_hi, T.f1_lo, fo + i), R1[(k1 + l1 - 2 * i - 1) * M1 + l1]);
-                acc = A::neg(acc);
-            } else {
-                // + sum_i f0[k1][l1][i] T[k1+l1-2i+1][l1]
-                const int imax = l1 < k1 ? l1 : k1;
-                for (int i = 0; i <= imax; ++i) {
-                    const int g1 = k1 + l1 - 2 * i + 1;
-                    if (g1 > GM) continue;
-                    acc = A::madd(acc, A::ld(T.f0_hi, T.f0_lo, fo + i), R1[g1 * M1 + l1]);
-                }
+    // (A) second axis: Y[r][l2] = sum_i f[k2][l2][i] S[g1][k2 + l2 - 2i +- 1]
+    // over the i whose g2 stays inside row g1 (lanes over rows)
+    {
+        const int off = pass == 0 ? 1 : -1;
+        for (int task = tid; task < M1 * nrp; task += nt) {
+            const int l2 = task / nrp, r = task - l2 * nrp;
+            const int g1 = par + 2 * r;
+            const int imax = pass == 0 ? (l2 < k2 ? l2 : k2) : (l2 < k2 - 1 ? l2 : k2 - 1);
+            const int over = k2 + l2 + off + g1 - GM;  // g2 <= GM - g1  <=>  2i >= over
+            const int ilo = over > 0 ? (over + 1) >> 1 : 0;
+            const double* fr = sF + 2 * (l2 * M1);
+            const double* sr = sS + 2 * (DDShape::row_off(M, par, r) + k2 + l2 + off);
+            Acc2 a{0.0, 0.0};
+            for (int i = ilo; i <= imax; ++i) dot2(a, fr[2 * i], fr[2 * i + 1], sr[-4 * i], sr[-4 * i + 1]);
+            const dd v = acc2_value(a);
+            sY[2 * (r * M1 + l2)] = v.hi;
+            sY[2 * (r * M1 + l2) + 1] = v.lo;
+        }
+    }
+    __syncthreads();
+    // (B) T[r][l1] = sum_{l2 <= M - l1} (-1)^{|l|} alpha_l Y[r][l2], two l1 per thread
+    {
+        const int npair = (M1 + 1) >> 1;
+        for (int task = tid; task < npair * nrp; task += nt) {
+            const int q = task / nrp, r = task - q * nrp;
+            const int l1 = 2 * q;
+            const double* yr = sY + 2 * (r * M1);
+            const double* a0 = sAR + l1 * M1;
+            const double* a1 = a0 + M1;  // zero where l1 + 1 + l2 > M (a zero row past M)
+            Acc2 u{0.0, 0.0}, v{0.0, 0.0};
+            for (int l2 = 0; l2 <= M - l1; ++l2) {
+                const double yh = yr[2 * l2], yl = yr[2 * l2 + 1];
+                dot2(u, a0[l2], yh, yl);
+                dot2(v, a1[l2], yh, yl);
+            }
+            const dd tu = acc2_value(u), tv = acc2_value(v);
+            sS[2 * (r * M1 + l1)] = tu.hi;
+            sS[2 * (r * M1 + l1) + 1] = tu.lo;
+            if (l1 + 1 <= M) {
+                sS[2 * (r * M1 + l1 + 1)] = tv.hi;
+                sS[2 * (r * M1 + l1 + 1) + 1] = tv.lo;
             }
         }
-        sG[task] = acc;
+    }
+    __syncthreads();
+    // (C) first axis for the (k1, l1) whose rows have parity par:
+    //   pass 0: - sum_i f1[k1][l1][i] T[k1 + l1 - 2i - 1][l1]
+    //   pass 1: + sum_i f0[k1][l1][i] T[k1 + l1 - 2i + 1][l1]
+    // with f[k1][l1][i] = C(l1, i) f[k1][i][i]; one task per (k1, l1 of that parity)
+    const int nk1 = M - k2 + 1;
+    const int H = (M1 + 1) >> 1;
+    for (int task = tid; task < nk1 * H; task += nt) {
+        const int k1 = task / H, q = task - k1 * H;
+        const int l1 = 2 * q + ((par + k1 + 1) & 1);
+        if (l1 > M) {
+            sY[2 * task] = 0.0;
+            sY[2 * task + 1] = 0.0;
+            continue;
+        }
+        Acc2 a{0.0, 0.0};
+        const double* bn = sBin + l1 * M1;
+        const double* fd = sFd + 2 * (k1 * M1);
+        if (pass == 0) {
+            const int imax = l1 < k1 - 1 ? l1 : k1 - 1;
+            for (int i = 0; i <= imax; ++i) {
+                const int r = (k1 + l1 - 2 * i - 1 - par) >> 1;
+                const dd f = dd_mul_d(dd_make(fd[2 * i], fd[2 * i + 1]), bn[i]);
+                dot2(a, f.hi, f.lo, sS[2 * (r * M1 + l1)], sS[2 * (r * M1 + l1) + 1]);
+            }
+            a.s = -a.s;
+            a.c = -a.c;
+        } else {
+            const int imax = l1 < k1 ? l1 : k1;
+            const int i0 = k1 + l1 + 1 > GM ? 1 : 0;
+            for (int i = i0; i <= imax; ++i) {
+                const int r = (k1 + l1 - 2 * i + 1 - par) >> 1;
+                const dd f = dd_mul_d(dd_make(fd[2 * i], fd[2 * i + 1]), bn[i]);
+                dot2(a, f.hi, f.lo, sS[2 * (r * M1 + l1)], sS[2 * (r * M1 + l1) + 1]);
+            }
+        }
+        const dd v = acc2_value(a);
+        sY[2 * task] = v.hi;
+        sY[2 * task + 1] = v.lo;
     }
     __syncthreads();
     // partial over l1 for every k1 of this k2 -> global (hi, lo)
     double* gp = B.gpart + ((long)j * 4 + (pass * 2 + par)) * K * 2;
     for (int k1 = tid; k1 < nk1; k1 += nt) {
-        R g = A::zero();
-        for (int l1 = 0; l1 <= M; ++l1) g = A::add(g, sG[k1 * M1 + l1]);
+        Acc2 a{0.0, 0.0};
+        for (int q = 0; q < H; ++q) dot2(a, 1.0, sY[2 * (k1 * H + q)], sY[2 * (k1 * H + q) + 1]);
+        const dd g = acc2_value(a);
         const int k = ctri(k1, k2);
-        A::st(gp + 2 * k, g);
+        gp[2 * k] = g.hi;
+        gp[2 * k + 1] = g.lo;
     }
 }
 
@@ -1335,23 +1446,18 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
         launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();
     }
-    // the factor slice goes to LDS when it fits
-    const size_t elem = sizeof(dd);
-    const size_t base = (size_t)T.K + 2 * (size_t)T.KG + (size_t)M1 * M1;
-    const bool fslice = (base + (size_t)M1 * M1) * elem <= 150 * 1024;
-    const size_t shmem = elem * (base + (fslice ? (size_t)M1 * M1 : 0));
-    const void* fn = fslice ? (const void*)k_stage2_dd<true> : (const void*)k_stage2_dd<false>;
+    if (B.interact || !B.s_self_lo) return hipErrorInvalidValue;  // single vortices only
+    const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0).total;
     if (shmem > 64 * 1024) {
-        // large orders stage up to ~150 KB of LDS
-        hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_dd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)shmem);
         if (ea != hipSuccess) {
             (void)hipGetLastError();
             report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
             return ea;
         }
     }
-    if (fslice) launch_kernel((k_stage2_dd<true>), grid, dim3(512), shmem, st, T, B, A);
-    else launch_kernel((k_stage2_dd<false>), grid, dim3(512), shmem, st, T, B, A);
+    launch_kernel(k_stage2_dd, grid, dim3(kDDThreads), shmem, st, T, B, A);
     return hipGetLastError();
 }
 

@@ -400,6 +400,27 @@ def test_single_particle_orders_sampled_rows(env, orc, M, prec):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_dense16_long_horizon_golden(env, prec, tol):
+    """16 strongly overlapping order-5 vortices stepped 1200 RK4 steps against
+    the oracle's end point stored in tests/golden/dense16_rk4_1200.json
+    (written by make_dense16.py from the oracle alone): the drift, the pair
+    interaction and the moment growth of a dense field, over a long horizon."""
+    import json
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_dense16
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense16_rk4_1200.json")) as f:
+        gold = json.load(f)
+    w = make_dense16.config()
+    x_r, m_r = np.array(gold["x"]), np.array(gold["mom"])
+    x_g, m_g = gpu_step(env, w, 0.0, gold["steps"], prec)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * gold["steps"] * w.dt)
+    assert normwise(w.M, lam_t, m_r, m_g) <= tol
+    assert np.abs(x_g - x_r).max() <= tol * max(1.0, np.abs(x_r).max())
+    # circulation: dM_00 is written as zero, so it holds bit for bit
+    assert np.array_equal(m_g[:, 0], w.mom[:, 0])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
 def test_random_multi_64_sampled(env, orc, prec, tol):
     from paper_1010_2475_amd import workloads as wl
     w = wl.random_multi()
