@@ -215,6 +215,14 @@ __device__ __forceinline__ void dot2(Acc2& a, double x, double yh, double yl)
     a.c += es + t;
 }
 
+// a += b (two partial sums of one compensated sum)
+__device__ __forceinline__ void acc2_merge(Acc2& a, const Acc2& b)
+{
+    const dd t = two_sum(a.s, b.s);
+    a.s = t.hi;
+    a.c += b.c + t.lo;
+}
+
 // the accumulated value as a normalised double-double
 __device__ __forceinline__ dd acc2_value(const Acc2& a) { return two_sum(a.s, a.c); }
 
@@ -444,41 +452,76 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
     double* sFd = smem + L.fd;
 
     // fills: S rows of parity par, the second-axis factor slice, signed alpha,
-    // binomials and the first-axis diagonals
+    // binomials and the first-axis diagonals.  Every global load of a thread
+    // is issued before its first LDS store (clamped addresses, zeros selected
+    // afterwards), so the fill costs about one L2 round trip.
     {
+        constexpr int MM1 = MMVM_MAX_ORDER + 1;
+        constexpr int NS = (MM1 * (2 * MMVM_MAX_ORDER + 1) + kDDThreads - 1) / kDDThreads;
+        constexpr int NQ = (MM1 * MM1 + kDDThreads - 1) / kDDThreads;
+        constexpr int NA = ((MM1 + 1) * MM1 + kDDThreads - 1) / kDDThreads;
         const double* ssh = B.s_self + (long)j * T.KG;
         const double* ssl = B.s_self_lo + (long)j * T.KG;
-        for (int e = tid; e < nrp * (GM + 1); e += nt) {
-            const int r = e / (GM + 1), g2 = e - r * (GM + 1);
-            const int g1 = par + 2 * r;
-            if (g1 + g2 > GM) continue;
-            const int g = ctri(g1, g2), o = DDShape::row_off(M, par, r) + g2;
-            const bool z = g == 0;
-            sS[2 * o] = z ? 0.0 : ssh[g];
-            sS[2 * o + 1] = z ? 0.0 : ssl[g];
-        }
         const double* fh = (pass == 0 ? T.f0_hi : T.f1_hi) + (long)k2 * M1 * M1;
         const double* fl = (pass == 0 ? T.f0_lo : T.f1_lo) + (long)k2 * M1 * M1;
-        for (int e = tid; e < M1 * M1; e += nt) {
-            sF[2 * e] = fh[e];
-            sF[2 * e + 1] = fl[e];
-        }
         const double* al = B.alpha[S.cur] + (long)j * K;
-        for (int e = tid; e < (M1 + 1) * M1; e += nt) {
-            const int l1 = e / M1, l2 = e - l1 * M1;
-            double a = 0.0;
-            if (l1 + l2 <= M) {
-                a = al[ctri(l1, l2)];
-                if ((l1 + l2) & 1) a = -a;
-            }
-            sAR[e] = a;
-        }
         const double* dh = pass == 0 ? T.fd1 : T.fd0;
         const double* dl = pass == 0 ? T.fd1_lo : T.fd0_lo;
-        for (int e = tid; e < M1 * M1; e += nt) {
-            sBin[e] = T.binom[e];
-            sFd[2 * e] = dh[e];
-            sFd[2 * e + 1] = dl[e];
+        const int nS = nrp * (GM + 1), nQ = M1 * M1, nA = (M1 + 1) * M1;
+        double vsh[NS], vsl[NS], vfh[NQ], vfl[NQ], vbn[NQ], vdh[NQ], vdl[NQ], va[NA];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int e = tid + u * kDDThreads;
+            const int r = e / (GM + 1), g2 = e - r * (GM + 1);
+            const int g1 = par + 2 * r;
+            const int g = (e < nS && g1 + g2 <= GM) ? ctri(g1, g2) : 0;
+            vsh[u] = ssh[g];
+            vsl[u] = ssl[g];
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int e = tid + u * kDDThreads;
+            const int ec = e < nQ ? e : 0;
+            vfh[u] = fh[ec];
+            vfl[u] = fl[ec];
+            vbn[u] = T.binom[ec];
+            vdh[u] = dh[ec];
+            vdl[u] = dl[ec];
+        }
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * kDDThreads;
+            const int l1 = e / M1, l2 = e - l1 * M1;
+            va[u] = al[(e < nA && l1 + l2 <= M) ? ctri(l1, l2) : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int e = tid + u * kDDThreads;
+            const int r = e / (GM + 1), g2 = e - r * (GM + 1);
+            const int g1 = par + 2 * r;
+            if (e < nS && g1 + g2 <= GM) {
+                const int o = DDShape::row_off(M, par, r) + g2;
+                const bool z = g1 + g2 == 0;
+                sS[2 * o] = z ? 0.0 : vsh[u];
+                sS[2 * o + 1] = z ? 0.0 : vsl[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int e = tid + u * kDDThreads;
+            if (e < nQ) {
+                sF[2 * e] = vfh[u];
+                sF[2 * e + 1] = vfl[u];
+                sBin[e] = vbn[u];
+                sFd[2 * e] = vdh[u];
+                sFd[2 * e + 1] = vdl[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * kDDThreads;
+            const int l1 = e / M1, l2 = e - l1 * M1;
+            if (e < nA) sAR[e] = l1 + l2 <= M ? (((l1 + l2) & 1) ? -va[u] : va[u]) : 0.0;
         }
     }
     __syncthreads();
@@ -494,8 +537,15 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             const int ilo = over > 0 ? (over + 1) >> 1 : 0;
             const double* fr = sF + 2 * (l2 * M1);
             const double* sr = sS + 2 * (DDShape::row_off(M, par, r) + k2 + l2 + off);
-            Acc2 a{0.0, 0.0};
-            for (int i = ilo; i <= imax; ++i) dot2(a, fr[2 * i], fr[2 * i + 1], sr[-4 * i], sr[-4 * i + 1]);
+            // two independent chains (even and odd i) keep more loads in flight
+            Acc2 a{0.0, 0.0}, b{0.0, 0.0};
+            int i = ilo;
+            for (; i < imax; i += 2) {
+                dot2(a, fr[2 * i], fr[2 * i + 1], sr[-4 * i], sr[-4 * i + 1]);
+                dot2(b, fr[2 * i + 2], fr[2 * i + 3], sr[-4 * i - 4], sr[-4 * i - 3]);
+            }
+            if (i == imax) dot2(a, fr[2 * i], fr[2 * i + 1], sr[-4 * i], sr[-4 * i + 1]);
+            acc2_merge(a, b);
             const dd v = acc2_value(a);
             sY[2 * (r * M1 + l2)] = v.hi;
             sY[2 * (r * M1 + l2) + 1] = v.lo;
@@ -511,12 +561,24 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             const double* yr = sY + 2 * (r * M1);
             const double* a0 = sAR + l1 * M1;
             const double* a1 = a0 + M1;  // zero where l1 + 1 + l2 > M (a zero row past M)
-            Acc2 u{0.0, 0.0}, v{0.0, 0.0};
-            for (int l2 = 0; l2 <= M - l1; ++l2) {
+            // even and odd l2 in separate chains
+            Acc2 u{0.0, 0.0}, v{0.0, 0.0}, u1{0.0, 0.0}, v1{0.0, 0.0};
+            int l2 = 0;
+            for (; l2 < M - l1; l2 += 2) {
+                const double yh = yr[2 * l2], yl = yr[2 * l2 + 1];
+                const double zh = yr[2 * l2 + 2], zl = yr[2 * l2 + 3];
+                dot2(u, a0[l2], yh, yl);
+                dot2(v, a1[l2], yh, yl);
+                dot2(u1, a0[l2 + 1], zh, zl);
+                dot2(v1, a1[l2 + 1], zh, zl);
+            }
+            if (l2 == M - l1) {
                 const double yh = yr[2 * l2], yl = yr[2 * l2 + 1];
                 dot2(u, a0[l2], yh, yl);
                 dot2(v, a1[l2], yh, yl);
             }
+            acc2_merge(u, u1);
+            acc2_merge(v, v1);
             const dd tu = acc2_value(u), tv = acc2_value(v);
             sS[2 * (r * M1 + l1)] = tu.hi;
             sS[2 * (r * M1 + l1) + 1] = tu.lo;
@@ -1446,7 +1508,8 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
         launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();
     }
-    if (B.interact || !B.s_self_lo) return hipErrorInvalidValue;  // single vortices only
+    // single vortices only; the fill is sized for kDDThreads threads and orders <= MMVM_MAX_ORDER
+    if (B.interact || !B.s_self_lo || T.M > MMVM_MAX_ORDER) return hipErrorInvalidValue;
     const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0).total;
     if (shmem > 64 * 1024) {
         hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_dd, hipFuncAttributeMaxDynamicSharedMemorySize,
