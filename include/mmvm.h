@@ -156,10 +156,27 @@ mmvm_status mmvm_server_destroy(mmvm_server* srv);
  * Kernel timing (profiling aid).  While enabled, every kernel launch of the
  * library is bracketed by HIP events on its stream; mmvm_timing_get waits for
  * them and returns the summed duration and launch count of one kernel
- * ("prep", "self", "pair", "stage2").  Enabling clears the totals.
- * MMVM_ENOTFOUND if the kernel has not run while enabled. */
+ * ("prep", "self", "pair", "stage2", "emit", "apply", "solo").  Enabling
+ * clears the totals.  MMVM_ENOTFOUND if the kernel has not run while enabled. */
 mmvm_status mmvm_timing_enable(int32_t on);
 mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Launch-shape autotuning of the pair kernel (the all-pairs interaction of
+ * eq:Final_CrossCoef): how many wavefronts share the sources of one target
+ * and how many targets a workgroup holds.  On by default (the environment
+ * variable MMVM_AUTOTUNE=0 starts a process with it off).  The first launch
+ * for a new key (order, precision, vortex count rounded up to a power of two)
+ * times every candidate shape on the caller's stream with the caller's
+ * inputs and synchronises that stream once; the fastest shape is kept for the
+ * rest of the process, so a key always runs the same shape (and gives the
+ * same bits).  Callers that capture launches into a graph should make one
+ * uncaptured call per key first.  With tuning off a fixed default shape runs.
+ * mmvm_autotune_report writes one text line per tuned key (shape, its time
+ * and the default shape's time, in microseconds) into buf, NUL-terminated;
+ * buf == NULL just sets *needed; MMVM_EINVAL if cap is too small. */
+mmvm_status mmvm_autotune_enable(int32_t on);
+mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed);
 
 /* Human-readable name of a status code (static string). */
 const char* mmvm_status_string(mmvm_status s);

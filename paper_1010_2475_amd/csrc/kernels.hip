@@ -311,22 +311,27 @@ hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd,
 }
 
 template <int M>
-hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
+hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
 
 bool pair_order_supported(int M) { return M >= 0 && M <= kMaxPairOrder; }
 
-hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
+hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
     switch (T.M) {
-    case 0: return launch_pair_M<0>(T, B, cur, f32, st);
-    case 1: return launch_pair_M<1>(T, B, cur, f32, st);
-    case 2: return launch_pair_M<2>(T, B, cur, f32, st);
-    case 3: return launch_pair_M<3>(T, B, cur, f32, st);
-    case 4: return launch_pair_M<4>(T, B, cur, f32, st);
-    case 5: return launch_pair_M<5>(T, B, cur, f32, st);
-    case 6: return launch_pair_M<6>(T, B, cur, f32, st);
+    case 0: return launch_pair_M<0>(T, B, cur, f32, sh, st);
+    case 1: return launch_pair_M<1>(T, B, cur, f32, sh, st);
+    case 2: return launch_pair_M<2>(T, B, cur, f32, sh, st);
+    case 3: return launch_pair_M<3>(T, B, cur, f32, sh, st);
+    case 4: return launch_pair_M<4>(T, B, cur, f32, sh, st);
+    case 5: return launch_pair_M<5>(T, B, cur, f32, sh, st);
+    case 6: return launch_pair_M<6>(T, B, cur, f32, sh, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
+{
+    return launch_pair_shape(T, B, cur, f32, pair_shape_for(T, B, cur, f32, st), st);
 }
 
 // ---------------------------------------------------------------------------

@@ -105,8 +105,22 @@ struct ApplyArgs {
 bool stage2_fuses_emit(int M, bool dd, bool solo);
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st);
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st);
-// pair velocity-derivative table (N > 1); f32 = mixed precision
+// pair velocity-derivative table (N > 1); f32 = mixed precision.  Launch
+// shape: split wavefronts per target (they share its sources), tpb targets
+// per workgroup; launch_pair takes the shape the autotuner picked for
+// (order, precision, N).
+struct PairShape {
+    int split = 1, tpb = 4;
+};
+constexpr int kPairMaxThreads = 256;  // the kernel keeps up to 256 VGPRs + AGPRs per lane
+inline bool pair_shape_valid(PairShape s)
+{
+    return s.split >= 1 && s.tpb >= 1 && (s.split & (s.split - 1)) == 0 && 64 * s.split * s.tpb <= kPairMaxThreads;
+}
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
+hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
+// the autotuner's shape for this launch (times the candidates on first use of a key)
+PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 // orders whose stage-2 kernel computes the self table itself
 constexpr int kMaxSmallOrder = 10;
 // Persistent RK4 of independent single vortices (one workgroup per solve, all

@@ -34,11 +34,17 @@ constexpr int kSeriesTerms = 56;
 // which is D^g of the source's velocity smoothed by the target Gaussian, in
 // the target's lambda units.
 // ---------------------------------------------------------------------------
+// Launch shape (PairShape): split wavefronts share the sources of one target
+// (wave q of a target takes the sources q*64 + lane, stepping by 64 split);
+// their wavefront sums meet in LDS and are added in wave order, so a shape
+// always gives the same bits.  A workgroup holds tpb targets.
 template <int M, typename R>
-__global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ xs, const double* __restrict__ lam2,
-                                              const R* __restrict__ aT, const double* __restrict__ kap0,
-                                              const double* __restrict__ kap1, const double* __restrict__ hol,
-                                              const double* __restrict__ rcp, double* __restrict__ spair)
+__global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, const double* __restrict__ xs,
+                                                          const double* __restrict__ lam2, const R* __restrict__ aT,
+                                                          const double* __restrict__ kap0,
+                                                          const double* __restrict__ kap1,
+                                                          const double* __restrict__ hol,
+                                                          const double* __restrict__ rcp, double* __restrict__ spair)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -48,11 +54,14 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
     constexpr bool F32 = std::is_same<R, float>::value;
     constexpr double kInvPi = 0.318309886183790671537767526745;
 
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (j >= N) return;  // uniform per wavefront
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tpb = (blockDim.x >> 6) / split;
+    const int jt = wave / split, sp = wave - jt * split;
+    const int j = blockIdx.x * tpb + jt;
+    const bool live = j < N;  // uniform per wavefront; every wave reaches the barrier below
+    const int jc = live ? j : 0;
 
-    const double xj1 = xs[2 * j], xj2 = xs[2 * j + 1], lj2 = lam2[j];
+    const double xj1 = xs[2 * jc], xj2 = xs[2 * jc + 1], lj2 = lam2[jc];
     const double ilj = 1.0 / sqrt(lj2);
     const double lj = lj2 * ilj;
 
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
     if constexpr (F32) sfor<0, KG>([&](auto g) { acc32[g] = 0.0f; });
     int pending = 0;
 
-    for (int jp = lane; jp < N; jp += 64) {
+    for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split) {
         if (jp == j) continue;
         const double lp2 = lam2[jp];
         const double c = lj2 + lp2;
@@ -199,6 +208,8 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
     if constexpr (F32) sfor<0, KG>([&](auto g) { acc[g] += (double)acc32[g]; });
 
     // wavefront reduction over the sources held by the 64 lanes
+    extern __shared__ double red_pair[];  // [waves][KG] when split > 1
+    double* out = split == 1 ? spair + (long)jc * KG : red_pair + wave * KG;
     sfor<1, KG>([&](auto g) {
         double v = acc[g];
         v += __shfl_xor(v, 32, 64);
@@ -207,22 +218,37 @@ __global__ __launch_bounds__(256) void k_pair(int N, const double* __restrict__ 
         v += __shfl_xor(v, 4, 64);
         v += __shfl_xor(v, 2, 64);
         v += __shfl_xor(v, 1, 64);
-        if (lane == (g & 63)) spair[(long)j * KG + g] = v;
+        if (lane == (g & 63) && (live || split > 1)) out[g] = v;
     });
-    if (lane == 0) spair[(long)j * KG] = 0.0;
+    if (split == 1) {
+        if (live && lane == 0) spair[(long)j * KG] = 0.0;
+        return;
+    }
+    __syncthreads();
+    if (!live || sp != 0) return;
+    for (int g = lane; g < KG; g += 64) {
+        double v = 0.0;
+        if (g > 0)
+            for (int q = 0; q < split; ++q) v += red_pair[(wave + q) * KG + g];
+        spair[(long)j * KG + g] = v;
+    }
 }
 
 template <int M>
-hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
+hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
-    const int wpb = 4;
-    dim3 grid((B.N + wpb - 1) / wpb);
+    constexpr int GM = M == 0 ? 1 : 2 * M;
+    constexpr int KG = (GM + 1) * (GM + 2) / 2;
+    if (!pair_shape_valid(sh)) return hipErrorInvalidValue;
+    const int waves = sh.split * sh.tpb;
+    dim3 grid((B.N + sh.tpb - 1) / sh.tpb);
+    const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;
     if (f32)
-        launch_kernel((k_pair<M, float>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT32[cur], T.kap0,
-                           T.kap1, T.hol, T.rcp, B.s_pair);
+        launch_kernel((k_pair<M, float>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
+                      B.alphaT32[cur], T.kap0, T.kap1, T.hol, T.rcp, B.s_pair);
     else
-        launch_kernel((k_pair<M, double>), grid, dim3(64 * wpb), 0, st, B.N, B.xs, B.lam2[cur], B.alphaT[cur], T.kap0,
-                           T.kap1, T.hol, T.rcp, B.s_pair);
+        launch_kernel((k_pair<M, double>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
+                      B.alphaT[cur], T.kap0, T.kap1, T.hol, T.rcp, B.s_pair);
     return hipGetLastError();
 }
 

@@ -2,5 +2,6 @@
 #include "pair.hpp"
 
 namespace mmvm {
-template hipError_t launch_pair_M<0>(const DevTables&, const StageBufs&, int, bool, hipStream_t);
+template hipError_t launch_pair_M<0>(const DevTables&, const StageBufs&, int, bool, PairShape,
+                                               hipStream_t);
 }

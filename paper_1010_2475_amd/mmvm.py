@@ -51,7 +51,7 @@ _lib = None
 
 SYMBOLS = ["mmvm_coeffs", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
            "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
-           "mmvm_status_string"]
+           "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_status_string"]
 
 
 def lib():
@@ -77,6 +77,8 @@ def lib():
     L.mmvm_server_destroy.argtypes = [vp]
     L.mmvm_timing_enable.argtypes = [ctypes.c_int32]
     L.mmvm_timing_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.mmvm_autotune_enable.argtypes = [ctypes.c_int32]
+    L.mmvm_autotune_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mmvm_status_string.argtypes = [ctypes.c_int]
     L.mmvm_status_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -162,6 +164,19 @@ def sync(stream=None):
 
 def timing_enable(on):
     _check(lib().mmvm_timing_enable(1 if on else 0), "mmvm_timing_enable")
+
+
+def autotune_enable(on):
+    _check(lib().mmvm_autotune_enable(1 if on else 0), "mmvm_autotune_enable")
+
+
+def autotune_report():
+    """The tuned launch shapes, one text line per key."""
+    need = ctypes.c_size_t(0)
+    _check(lib().mmvm_autotune_report(None, ctypes.c_size_t(0), ctypes.byref(need)), "mmvm_autotune_report")
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().mmvm_autotune_report(buf, ctypes.c_size_t(need.value), ctypes.byref(need)), "mmvm_autotune_report")
+    return buf.value.decode()
 
 
 def timing_get(kernel):

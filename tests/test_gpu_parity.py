@@ -400,6 +400,37 @@ def test_single_particle_orders_sampled_rows(env, orc, M, prec):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_autotuned_pair_shape_matches_oracle(env, orc, prec, tol):
+    """The pair kernel under the shape the autotuner picks (sources of a
+    target split over several wavefronts) and under the fixed default shape:
+    both against the oracle on sampled rows, equal to each other to rounding,
+    and the tuned shape repeats its bits."""
+    torch, mm = env
+    w = rand_workload(61, 300, 4, spread=4.0)
+    t = 0.1
+    mm.autotune_enable(False)
+    try:
+        _, d_def = gpu_rhs(env, w, t, prec)
+    finally:
+        mm.autotune_enable(True)
+    _, d_a = gpu_rhs(env, w, t, prec)
+    _, d_b = gpu_rhs(env, w, t, prec)
+    assert np.array_equal(d_a, d_b)
+    rep = mm.autotune_report()
+    assert ("pair order=4 prec=%s n<=512" % ("mixed" if prec else "fp64")) in rep, rep
+    js = [0, 151, 299]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, _ = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)[js]
+    assert normwise(w.M, lam_t, d.reshape(3, w.K), d_a[js]) <= tol
+    assert normwise(w.M, lam_t, d.reshape(3, w.K), d_def[js]) <= tol
+    # every vortex: two results each within the bar of the exact one differ by at most twice the bar
+    lam_all = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    assert normwise(w.M, lam_all, d_def, d_a) <= (1e-13 if prec == 0 else 2 * MIXED_TOL)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
 def test_dense16_long_horizon_golden(env, prec, tol):
     """16 strongly overlapping order-5 vortices stepped 1200 RK4 steps against
     the oracle's end point stored in tests/golden/dense16_rk4_1200.json
