@@ -893,16 +893,19 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     static_assert(16 * ((kS2MaxOrder + 16) / 16) <= 64, "a row of alpha fits a wavefront");
 
     const double2* gT = reinterpret_cast<const double2*>(T.t0d);
+    // Operand rows past the k-steps in use are never read by the products, so
+    // their loads only need to stay inside the tables: the indices are clamped
+    // (lane-dependent arithmetic, no branch around a load).
+    const int capT = tz.T0R * (TP / 2) - 1;
     if constexpr (APPLY) {
         // finish the previous stage for the moments with m1 of this parity; the
         // row-0 workgroup of each parity writes their state and signed moments.
         // All loads first; the powers of lambda come from a table built with
         // the same sequential products as the emit kernel.
-        const double wts[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-        const double cn[3] = {0.5, 0.5, 1.0};
-        const int K = T.K;
+        // RK4 weight of this stage and node of the next one
+        const double wst = (P.stage == 0 || P.stage == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
+        const double cnx = P.stage < 2 ? 0.5 : 1.0;
         const bool writer = r == 0;
-        const bool need_acc = P.stage == 3 || (writer && P.stage > 0);
         double2 vt2[kRowSlots];
         double pg[kRowSlots][4], pc[kRowSlots], py[kRowSlots], pa[kRowSlots];
         const long LL = (long)LP * LP;
@@ -912,14 +915,18 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
 #pragma unroll
         for (int q = 0; q < kRowSlots; ++q) {
             const int m1p = wave + kSelfWaves * q, m1 = p1 + 2 * m1p, m2 = lane;
-            const bool on = m1p < 4 * ks;
-            vt2[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
+            vt2[q] = gT[min((sh1 + m1p) * (TP / 2) + lane, capT)];
             const int d = m1 + m2 <= M ? m1 * LP + m2 : 0;  // dense (k1, k2) position
 #pragma unroll
             for (int h = 0; h < 4; ++h) pg[q][h] = gpj[h * LL + d];
             pc[q] = T.c1d[d];
             py[q] = yj[d];
-            pa[q] = need_acc ? aj[d] : 0.0;
+            pa[q] = aj[d];  // used from stage 1 on
+        }
+#pragma unroll
+        for (int q = 0; q < kRowSlots; ++q) {
+            const int m1p = wave + kSelfWaves * q;
+            if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt2[q];
         }
         __shared__ double pw[2][MMVM_MAX_ORDER + 1];  // lambda_prev^s / lambda_prev^2, lambda_next^{-s}
         if (tid <= M) {
@@ -946,28 +953,27 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
                 double nxt;
                 const long o = (long)j * LL + m1 * LP + m2;
                 if (P.stage < 3) {
-                    if (writer) B.accD[o] = P.stage == 0 ? wts[0] * val : pa[q] + wts[P.stage] * val;
-                    nxt = py[q] + cn[P.stage] * P.dt * val;
+                    if (writer) B.accD[o] = P.stage == 0 ? wst * val : pa[q] + wst * val;
+                    nxt = py[q] + cnx * P.dt * val;
                 } else {
-                    nxt = py[q] + P.dt * (pa[q] + wts[3] * val);
+                    nxt = py[q] + P.dt * (pa[q] + wst * val);
                     if (writer) B.ystate[1 - P.ycur][o] = nxt;
                 }
                 a = nxt * pw[1][s];
                 if (writer) B.alphaS[cur][(long)j * LP * LP + m2 * LP + m1] = (s & 1) ? -a : a;
             }
             if (lane < LP) sAl[m1p * LDA + lane] = a;
-            if (lane < TP / 2) reinterpret_cast<double2*>(sT0 + m1p * LDB)[lane] = vt2[q];
         }
     } else {
         // operands: rows copied as double2, all loads first
         const double2* gA = reinterpret_cast<const double2*>(B.alphaD[cur] + (long)j * sh.LA() * LP);
+        const int capA = sh.LA() * (LP / 2) - 1;
         double2 va[kRowSlots], vt[kRowSlots];
 #pragma unroll
         for (int q = 0; q < kRowSlots; ++q) {
             const int m1p = wave + kSelfWaves * q;
-            const bool on = m1p < 4 * ks;  // rows of the k-steps in use (all inside both tables)
-            va[q] = gA[(on && lane < LP / 2) ? (p1 + 2 * m1p) * (LP / 2) + lane : 0];
-            vt[q] = gT[(on && lane < TP / 2) ? (sh1 + m1p) * (TP / 2) + lane : 0];
+            va[q] = gA[min((p1 + 2 * m1p) * (LP / 2) + lane, capA)];
+            vt[q] = gT[min((sh1 + m1p) * (TP / 2) + lane, capT)];
         }
 #pragma unroll
         for (int q = 0; q < kRowSlots; ++q) {
