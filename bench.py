@@ -57,6 +57,30 @@ def self_flops(M):
     return 2 * macs
 
 
+# HBM traffic of the matrix-core stage-2 kernel (one launch = the 3 solves),
+# from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a
+# plain device copy of known size (bench.py --copy-calibration: 256 MiB read
+# and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
+# Valid only for the kernel sources it was taken on.
+TRAFFIC_STAGE2 = {"fetch_kib": 3262.8, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
+                  "write_scale": 262144.0 / 262146.0,
+                  "sources_sha256": {"kernels.hip": "284d86b41f82205330a483209ed32cb2ac6cdf7be52a3f02d768a2f610267fb3",
+                                     "kernels.hpp": "240c069c2e16d419f7565ccb75ab173e76e486577358f7cd7425cefcadd4b573"}}
+
+
+def stage2_traffic_bytes():
+    """Calibrated bytes per launch, or None once the kernel sources changed."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1010_2475_amd", "csrc")
+    for name, sha in TRAFFIC_STAGE2["sources_sha256"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
+    t = TRAFFIC_STAGE2
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def serve_leg(mm, wl, n_req, budget, slots, prec):
     """Replays the first n_req requests of the seeded request stream at their
     arrival times through the solve server; latency = arrival -> result ready."""
@@ -151,7 +175,21 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-budget-mb", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy (y = 1.0 * x over 256 MiB, five launches), the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes, and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 32 * 1024 * 1024  # doubles: 256 MiB read and 256 MiB written per launch
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload's solves are independent and this build "
               "measures one MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -210,11 +248,15 @@ def main():
         "kernels_ms_per_launch": {p: {k: (v[0] / v[1] if v[1] else None) for k, v in kernels[p].items()}
                                   for p in kernels},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                     "traffic": stage2_traffic_bytes() if dom == "stage2" else None,
                      "flops_per_launch": flops[dom], "avg_launch_ms": avg_ms,
                      "note": "algorithmic flops of the factorised contraction of the 3 vortices of one launch (the "
                              "matrix-core kernel also multiplies the zero padding of its operands); duration "
-                             "from runtime-stamped start/end events of each launch on its stream"},
+                             "from runtime-stamped start/end events of each launch on its stream; traffic = "
+                             "calibrated FETCH_SIZE + WRITE_SIZE bytes per launch (null once the kernel sources "
+                             "differ from the profiled ones), about 45x the algorithmic bytes: every launch "
+                             "refills the L2 of each of the 8 XCDs with the constant operand tables"},
     }
 
     if args.serve_requests > 0:
