@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -35,17 +36,62 @@ std::mutex g_tab_mu;
 std::map<std::pair<int, int>, std::unique_ptr<DevTablesOwner>> g_dev_tables;
 
 template <typename V>
-const double* upload(DevTablesOwner& o, const V& v, hipError_t& err)
+const typename V::value_type* upload(DevTablesOwner& o, const V& v, hipError_t& err)
 {
+    typedef typename V::value_type E;
     if (err != hipSuccess) return nullptr;
     void* p = nullptr;
-    size_t n = v.size() * sizeof(double);
-    if (n == 0) n = sizeof(double);
+    size_t n = v.size() * sizeof(E);
+    if (n == 0) n = sizeof(E);
     err = hipMalloc(&p, n);
     if (err != hipSuccess) return nullptr;
     o.bufs.push_back(p);
-    if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
-    return (const double*)p;
+    if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice);
+    return (const E*)p;
+}
+
+// Task lists of the double-double stage 2, one per workgroup (k2, pass, row
+// parity): steps A and C visit their (row, l2) and (k1, l1-slot) sums in
+// decreasing order of length, so the lanes of a wavefront run loops of about
+// equal trip count.  Entries (hi << 8 | lo), padded with -1.
+void dd_task_lists(int M, std::vector<int32_t>& la, std::vector<int32_t>& lc)
+{
+    const int M1 = M + 1, GM = 2 * M, H = (M1 + 1) >> 1;
+    la.assign((size_t)M1 * 4 * M1 * M1, -1);
+    lc.assign((size_t)M1 * 4 * M1 * H, -1);
+    std::vector<std::pair<int, int32_t>> v;
+    for (int k2 = 0; k2 <= M; ++k2)
+        for (int pass = 0; pass < 2; ++pass)
+            for (int par = 0; par < 2; ++par) {
+                const size_t b = ((size_t)k2 * 2 + pass) * 2 + par;
+                const int nrp = (2 * M - par) / 2 + 1, off = pass == 0 ? 1 : -1;
+                v.clear();
+                for (int l2 = 0; l2 <= M; ++l2)
+                    for (int r = 0; r < nrp; ++r) {
+                        const int g1 = par + 2 * r;
+                        const int imax = pass == 0 ? std::min(l2, k2) : std::min(l2, k2 - 1);
+                        const int over = k2 + l2 + off + g1 - GM;
+                        const int ilo = over > 0 ? (over + 1) >> 1 : 0;
+                        v.push_back(std::make_pair(std::max(0, imax - ilo + 1), (int32_t)((r << 8) | l2)));
+                    }
+                std::stable_sort(v.begin(), v.end(), [](const std::pair<int, int32_t>& a,
+                                                        const std::pair<int, int32_t>& c) { return a.first > c.first; });
+                for (size_t t = 0; t < v.size(); ++t) la[b * M1 * M1 + t] = v[t].second;
+                v.clear();
+                for (int k1 = 0; k1 <= M - k2; ++k1)
+                    for (int q = 0; q < H; ++q) {
+                        const int l1 = 2 * q + ((par + k1 + 1) & 1);
+                        int trip = 0;
+                        if (l1 <= M) {
+                            if (pass == 0) trip = std::min(l1, k1 - 1) + 1;
+                            else trip = std::min(l1, k1) + 1 - (k1 + l1 + 1 > GM ? 1 : 0);
+                        }
+                        v.push_back(std::make_pair(std::max(0, trip), (int32_t)((k1 << 8) | q)));
+                    }
+                std::stable_sort(v.begin(), v.end(), [](const std::pair<int, int32_t>& a,
+                                                        const std::pair<int, int32_t>& c) { return a.first > c.first; });
+                for (size_t t = 0; t < v.size(); ++t) lc[b * M1 * H + t] = v[t].second;
+            }
 }
 
 }  // namespace
@@ -77,6 +123,12 @@ mmvm_status device_tables(int M, const DevTables** out)
     d.fd1 = upload(*o, H.fd1, err);
     d.fd0_lo = upload(*o, H.fd0_lo, err);
     d.fd1_lo = upload(*o, H.fd1_lo, err);
+    {
+        std::vector<int32_t> la, lc;
+        if (M > kDDThreshold && M <= MMVM_MAX_ORDER) dd_task_lists(M, la, lc);
+        d.dd_la = upload(*o, la, err);
+        d.dd_lc = upload(*o, lc, err);
+    }
     {
         // zero-padded operands of the matrix-core stage 2 (see S2Shape)
         std::vector<double> wpad, cpad;

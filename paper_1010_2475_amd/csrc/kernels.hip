@@ -433,6 +433,9 @@ struct DDShape {
 };
 
 constexpr int kDDThreads = 1024;
+// task-list entries per thread: steps A (rows x l2 <= (M+1)^2) and C (k1 x l1 slots)
+constexpr int kDDTA = ((MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 1) + kDDThreads - 1) / kDDThreads;
+constexpr int kDDTC = ((MMVM_MAX_ORDER + 1) * ((MMVM_MAX_ORDER + 2) / 2) + kDDThreads - 1) / kDDThreads;
 
 // blockIdx.x = (k2, pass, par): pass 0 = Y half (f0 on the second axis, f1 on
 // the first, minus sign), pass 1 = X half; par = parity of the rows g1 this
@@ -456,6 +459,11 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
     double* sBin = smem + L.bin;
     double* sFd = smem + L.fd;
 
+    // this workgroup's task lists of steps A and C (longest sums first)
+    const int H = (M1 + 1) >> 1;
+    const int* la = T.dd_la + (long)blockIdx.x * M1 * M1;
+    const int* lc = T.dd_lc + (long)blockIdx.x * M1 * H;
+    int codeA[kDDTA], codeC[kDDTC];
     // fills: S rows of parity par, the second-axis factor slice, signed alpha,
     // binomials and the first-axis diagonals.  Every global load of a thread
     // is issued before its first LDS store (clamped addresses, zeros selected
@@ -474,6 +482,10 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
         const double* dl = pass == 0 ? T.fd1_lo : T.fd0_lo;
         const int nS = nrp * (GM + 1), nQ = M1 * M1, nA = (M1 + 1) * M1;
         double vsh[NS], vsl[NS], vfh[NQ], vfl[NQ], vbn[NQ], vdh[NQ], vdl[NQ], va[NA];
+#pragma unroll
+        for (int u = 0; u < kDDTA; ++u) codeA[u] = la[min(tid + u * kDDThreads, M1 * M1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kDDTC; ++u) codeC[u] = lc[min(tid + u * kDDThreads, M1 * H - 1)];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
             const int e = tid + u * kDDThreads;
@@ -534,8 +546,10 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
     // over the i whose g2 stays inside row g1 (lanes over rows)
     {
         const int off = pass == 0 ? 1 : -1;
-        for (int task = tid; task < M1 * nrp; task += nt) {
-            const int l2 = task / nrp, r = task - l2 * nrp;
+#pragma unroll
+        for (int u = 0; u < kDDTA; ++u) {
+            if (tid + u * kDDThreads >= M1 * nrp) break;
+            const int r = codeA[u] >> 8, l2 = codeA[u] & 255;
             const int g1 = par + 2 * r;
             const int imax = pass == 0 ? (l2 < k2 ? l2 : k2) : (l2 < k2 - 1 ? l2 : k2 - 1);
             const int over = k2 + l2 + off + g1 - GM;  // g2 <= GM - g1  <=>  2i >= over
@@ -599,9 +613,11 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
     //   pass 1: + sum_i f0[k1][l1][i] T[k1 + l1 - 2i + 1][l1]
     // with f[k1][l1][i] = C(l1, i) f[k1][i][i]; one task per (k1, l1 of that parity)
     const int nk1 = M - k2 + 1;
-    const int H = (M1 + 1) >> 1;
-    for (int task = tid; task < nk1 * H; task += nt) {
-        const int k1 = task / H, q = task - k1 * H;
+#pragma unroll
+    for (int u = 0; u < kDDTC; ++u) {
+        if (tid + u * kDDThreads >= nk1 * H) break;
+        const int k1 = codeC[u] >> 8, q = codeC[u] & 255;
+        const int task = k1 * H + q;
         const int l1 = 2 * q + ((par + k1 + 1) & 1);
         if (l1 > M) {
             sY[2 * task] = 0.0;

@@ -21,6 +21,8 @@ struct DevTables {
     const double* fd1;     // [M+1][M+1] f1[k][i][i]
     const double* fd0_lo;  // low parts of fd0, fd1 (double-double)
     const double* fd1_lo;
+    const int* dd_la;      // double-double stage 2: task lists of steps A and C per (k2, pass, parity)
+    const int* dd_lc;
     const double* wpad;    // matrix-core stage 2: banded factor operand [M+1][2][KA][LP] (k2, pass, g2, l2)
     const double* cpad;    // matrix-core stage 2: C(l, i) zero-padded [LP][LP]
     const double* t0d;     // matrix-core self table: Psi0 dense [T0R][TP] (a, b), zero beyond a + b <= T0N
