@@ -11,7 +11,8 @@ error against the FP64 oracle on sampled right-hand-side rows.  A served leg
 replays the first requests of the seeded Poisson request stream through the
 solve server and reports p50/p99 latency beside its throughput.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-requests R]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-requests R] [--no-configs]
+       [--no-cpu-baseline] [--no-error] [--copy-calibration]
 """
 import argparse
 import json
@@ -61,12 +62,12 @@ def self_flops(M):
 # from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
-# and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
+# and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262149 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3262.8, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
-                  "write_scale": 262144.0 / 262146.0,
-                  "sources_sha256": {"kernels.hip": "284d86b41f82205330a483209ed32cb2ac6cdf7be52a3f02d768a2f610267fb3",
-                                     "kernels.hpp": "240c069c2e16d419f7565ccb75ab173e76e486577358f7cd7425cefcadd4b573"}}
+TRAFFIC_STAGE2 = {"fetch_kib": 3271.2, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
+                  "write_scale": 262144.0 / 262149.0,
+                  "sources_sha256": {"kernels.hip": "65d763ab95384107b1dcfb4fc1a980f973d67c03634a7f48f14ac9668634a8d8",
+                                     "kernels.hpp": "0fdb691c5dbc198f8703be09f0e6c2ef2a333c3ed8210e6ead5819cd231b6df0"}}
 
 
 def stage2_traffic_bytes():
@@ -152,6 +153,31 @@ def measure(mm, torch, works, prec, steps, warmup):
     return t_b - t_a, [start.elapsed_time(end)], states
 
 
+def other_configs(mm, torch, wl):
+    """The other workloads at their full sizes, both precisions: whole-run
+    moment-updates/s with the state resident on the device (after 3 untimed
+    steps); the two-cluster run is cut to 50 of its 200 steps."""
+    dev = torch.device("cuda:0")
+    cases = (("single_quadrupole_M10_Re1000", wl.single_quadrupole(), 1000),
+             ("random_multi_N64_M6_Re500", wl.random_multi(), 500),
+             ("two_clusters_N4096_M4_Re2000", wl.two_clusters(), 50))
+    out = {}
+    for name, w, steps in cases:
+        r = {"N": w.N, "M": w.M, "steps": steps}
+        for pname, prec in (("mixed", mm.MIXED), ("fp64", mm.FP64)):
+            X = torch.tensor(w.x, device=dev)
+            Mo = torch.tensor(w.mom, device=dev)
+            mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, 3, X, Mo, prec)
+            mm.sync()
+            t_a = time.perf_counter()
+            mm.step(w.M, w.nu, w.lam0, 3 * w.dt, w.dt, steps, X, Mo, prec)
+            mm.sync()
+            secs = time.perf_counter() - t_a
+            r[pname] = {"moment_updates_per_s": w.N * w.K * steps / secs, "ms_per_step": 1e3 * secs / steps}
+        out[name] = r
+    return out
+
+
 def rhs_error(mm, torch, orc, w, x, mom, prec, t, rows):
     dev = torch.device("cuda:0")
     X = torch.tensor(x, device=dev)
@@ -173,6 +199,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip timing the other workloads")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-budget-mb", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -258,6 +285,10 @@ def main():
                              "differ from the profiled ones), about 45x the algorithmic bytes: every launch "
                              "refills the L2 of each of the 8 XCDs with the constant operand tables"},
     }
+
+    if not args.no_configs:
+        print("timing the other workloads", file=sys.stderr, flush=True)
+        out["other_configs"] = other_configs(mm, torch, wl)
 
     if args.serve_requests > 0:
         print("serving %d requests" % args.serve_requests, file=sys.stderr, flush=True)

@@ -31,7 +31,8 @@ def _requests():
             wl.random_multi(N=40, M=4, Re=300.0, seed=11, steps=90),
             wl.single_random(M=30, Re=2000.0, steps=60),
             wl.random_multi(N=150, M=3, Re=1000.0, seed=12, steps=50),
-            wl.random_multi(N=20, M=6, Re=500.0, seed=13, steps=80)]
+            wl.random_multi(N=20, M=6, Re=500.0, seed=13, steps=80),
+            wl.single_random(M=9, Re=300.0, seed=5, steps=110)]  # persistent small-order kernel
     return reqs
 
 
