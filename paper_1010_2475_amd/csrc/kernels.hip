@@ -33,6 +33,18 @@ __device__ __forceinline__ double inv_lambda_pow(double l2, int s)
     return p;
 }
 
+// x^s by binary exponentiation (at most 2 log2(s) dependent products)
+__device__ __forceinline__ double pow_uint(double x, int s)
+{
+    double r = 1.0;
+    while (s) {
+        if (s & 1) r *= x;
+        x *= x;
+        s >>= 1;
+    }
+    return r;
+}
+
 // The two dense layouts of the scaled moments read by the matrix-core kernels
 // (only allocated on that path): alphaD[m1][m2] and (-1)^{|l|} alpha at (l2, l1).
 __device__ __forceinline__ void store_dense_alpha(const StageBufs& B, int buf, int M, int j, int k1, int k2, double a)
@@ -916,12 +928,13 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     if constexpr (APPLY) {
         // finish the previous stage for the moments with m1 of this parity; the
         // row-0 workgroup of each parity writes their state and signed moments.
-        // All loads first; the powers of lambda come from a table built with
-        // the same sequential products as the emit kernel.
+        // All loads first; the powers of lambda come from a per-workgroup table
+        // (binary exponentiation: short dependency chains).
         // RK4 weight of this stage and node of the next one
         const double wst = (P.stage == 0 || P.stage == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
         const double cnx = P.stage < 2 ? 0.5 : 1.0;
         const bool writer = r == 0;
+        const double l0sq = B.lam0sq[j], nuj = B.nuv[j];  // issued with the operand loads
         double2 vt2[kRowSlots];
         double pg[kRowSlots][4], pc[kRowSlots], py[kRowSlots], pa[kRowSlots];
         const long LL = (long)LP * LP;
@@ -946,13 +959,10 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         }
         __shared__ double pw[2][MMVM_MAX_ORDER + 1];  // lambda_prev^s / lambda_prev^2, lambda_next^{-s}
         if (tid <= M) {
-            const double lam2p = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_prev;
-            const double lamp = sqrt(lam2p);
-            const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_next;
-            double lp = 1.0;
-            for (int e = 0; e < tid; ++e) lp *= lamp;
-            pw[0][tid] = lp / lam2p;
-            pw[1][tid] = inv_lambda_pow(lam2n, tid);
+            const double lam2p = l0sq + 4.0 * nuj * P.t_prev;
+            const double lam2n = l0sq + 4.0 * nuj * P.t_next;
+            pw[0][tid] = pow_uint(sqrt(lam2p), tid) / lam2p;
+            pw[1][tid] = pow_uint(1.0 / sqrt(lam2n), tid);
             if (writer && par == 0 && tid == 0) B.lam2[cur][j] = lam2n;
         }
         __syncthreads();
