@@ -25,14 +25,6 @@ namespace mmvm {
 // ---------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double inv_lambda_pow(double l2, int s)
-{
-    const double il = 1.0 / sqrt(l2);
-    double p = 1.0;
-    for (int e = 0; e < s; ++e) p *= il;
-    return p;
-}
-
 // x^s by binary exponentiation (at most 2 log2(s) dependent products)
 __device__ __forceinline__ double pow_uint(double x, int s)
 {
@@ -44,6 +36,9 @@ __device__ __forceinline__ double pow_uint(double x, int s)
     }
     return r;
 }
+
+// lambda^{-s} from lambda^2
+__device__ __forceinline__ double inv_lambda_pow(double l2, int s) { return pow_uint(1.0 / sqrt(l2), s); }
 
 // The two dense layouts of the scaled moments read by the matrix-core kernels
 // (only allocated on that path): alphaD[m1][m2] and (-1)^{|l|} alpha at (l2, l1).
@@ -1051,8 +1046,8 @@ hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, co
     return hipGetLastError();
 }
 
-// the last stage of a stepping call: y_{n+1} into the caller's moments (same
-// arithmetic, in the same order, as the emit kernel)
+// the last stage of a stepping call: y_{n+1} into the caller's moments (the
+// emit kernel's arithmetic)
 __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, ApplyArgs P)
 {
     const int j = blockIdx.x, K = T.K;
@@ -1068,9 +1063,7 @@ __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, 
         double g = gp[0] + gp[LL];
         g += gp[2 * LL];
         g += gp[3 * LL];
-        double lp = 1.0;  // lambda^{s-2}
-        for (int e = 0; e < s; ++e) lp *= lamp;
-        lp /= lam2p;
+        const double lp = pow_uint(lamp, s) / lam2p;  // lambda^{s-2}
         const double val = k == 0 ? 0.0 : (T.c1d[k1 * LP + k2] * g) * lp;
         P.mom_out[(long)j * K + k] = B.ystate[P.ycur][o] + P.dt * (B.accD[o] + (1.0 / 6.0) * val);
     }
@@ -1119,9 +1112,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
         } else {
             for (int q = 0; q < 4; ++q) g = A::add(g, A::ldst(gj + ((long)q * K + k) * 2));
         }
-        double lp = 1.0;  // lambda^{s-2}
-        for (int e = 0; e < s; ++e) lp *= lam;
-        lp /= lam2;
+        const double lp = pow_uint(lam, s) / lam2;  // lambda^{s-2}
         double val = A::hi(A::madd(A::zero(), A::ld(T.c1_hi, T.c1_lo, k), g)) * lp;
         if (B.interact) {  // drift, eq:last_termsimp: xdot_1 M_{k-e1} + xdot_2 M_{k-e2}
             double lq = lp * lam;  // lambda^{s-1}
@@ -1333,13 +1324,17 @@ __device__ __forceinline__ double small_value(const DevTables& T, const double* 
     constexpr int K = Sh::K, M1 = Sh::M1;
     const double* sP = smem + Sh::SP;
     const double* sAl = smem + Sh::AL;
-    double g = 0.0;
-    for (int l1 = 0; l1 < M1; ++l1) g += sP[k * M1 + l1] + sP[(K + k) * M1 + l1];
+    // the two halves' partial sums over l1 in two chains
+    double g = 0.0, h = 0.0;
+#pragma unroll
+    for (int l1 = 0; l1 < M1; ++l1) {
+        g += sP[k * M1 + l1];
+        h += sP[(K + k) * M1 + l1];
+    }
+    g += h;
     const int s = shell_of(k);
     const int k2 = k - s * (s + 1) / 2, k1 = s - k2;
-    double lp = 1.0;
-    for (int e = 0; e < s; ++e) lp *= lam;
-    lp /= lam2;
+    const double lp = pow_uint(lam, s) / lam2;
     double val = T.c1_hi[k] * g * lp;
     if (drift) {
         const double lq = lp * lam;
@@ -1387,9 +1382,9 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
 // without leaving the kernel.  The tables stay in LDS for the whole run; the
 // state y_n and the RK4 accumulator of moment k live in the registers of
 // thread k.  A single vortex does not move (its pair table and drift are
-// zero), so the centre is not touched.  Each stage is the arithmetic of
-// k_prep + k_stage2_small at the same stage times, so the two routes agree
-// bit for bit.
+// zero), so the centre is not touched.  Each stage computes what k_prep and
+// k_stage2_small compute at the same stage times (the same stage body and
+// power functions).
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(1024) void k_solo_rk4(DevTables T, const double* __restrict__ lam0sq,
