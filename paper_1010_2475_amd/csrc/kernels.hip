@@ -419,27 +419,38 @@ __device__ void centre_velocity(const double* al, const double* sp, int K, doubl
 // LDS layout of the double-double stage 2 (doubles; double-double values as
 // (hi, lo) pairs).  Rows r of the velocity-derivative table hold g1 = par + 2r
 // with g2 = 0 .. GM - g1 (row-packed); step B overwrites it with T.
+// With ctab (one workgroup per CU, 134.8 KB at order 40) the second-axis factor
+// slice is a full [M+1][M+1] rectangle and step C's binomials and first-axis
+// diagonals are staged in LDS too; without (two workgroups per CU, 79.4 KB),
+// the slice keeps only its band i <= min(l2, k2) and step C reads its tables
+// from L2.
 struct DDShape {
     int M1, nrp;
     int s, f, y, ar, bin, fd, total;
-    __host__ __device__ DDShape(int M, int par)
+    __host__ __device__ DDShape(int M, int par, bool ctab)
     {
         M1 = M + 1;
         nrp = (2 * M - par) / 2 + 1;
         const int m2 = M1 * M1;
         s = 0;                      // S, then T: nrp * M1 <= M1^2 pairs
-        f = s + 2 * m2;             // f[k2][l2][i] of the second axis: [M1][M1] pairs
-        y = f + 2 * m2;             // Y, then the partials of step C: [M1][M1] pairs
+        f = s + 2 * m2;             // f[k2][l2][i]: [M1][M1] pairs (ctab), else its band i <= min(l2, k2)
+        y = f + (ctab ? 2 * m2 : M1 * (M1 + 1));  // Y, then the partials of step C: [M1][M1] pairs
         ar = y + 2 * m2;            // (-1)^{|l|} alpha at (l1, l2), zero beyond the triangle: [M1 + 1][M1]
-        bin = ar + (M1 + 1) * M1;   // C(l, i): [M1][M1]
-        fd = bin + m2;              // f[k1][i][i] of the first axis: [M1][M1] pairs
-        total = fd + 2 * m2;
+        bin = ar + (M1 + 1) * M1;   // C(l, i): [M1][M1] (ctab)
+        fd = bin + (ctab ? m2 : 0);  // f[k1][i][i] of the first axis: [M1][M1] pairs (ctab)
+        total = fd + (ctab ? 2 * m2 : 0);
     }
     // start of row r (in pairs): rows have GM - par - 2r + 1 entries
     __host__ __device__ static int row_off(int M, int par, int r) { return r * (2 * M - par + 1) - r * (r - 1); }
+    // start of row l2 of the factor band (in pairs): rows have min(l2, k2) + 1 entries
+    __host__ __device__ static int band_off(int k2, int l2)
+    {
+        return l2 <= k2 + 1 ? l2 * (l2 + 1) / 2 : (k2 + 1) * (k2 + 2) / 2 + (l2 - k2 - 1) * (k2 + 1);
+    }
 };
 
 constexpr int kDDThreads = 1024;
+constexpr int kDDOneRound = 256;  // compute units of an MI355X
 // task-list entries per thread: steps A (rows x l2 <= (M+1)^2) and C (k1 x l1 slots)
 constexpr int kDDTA = ((MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 1) + kDDThreads - 1) / kDDThreads;
 constexpr int kDDTC = ((MMVM_MAX_ORDER + 1) * ((MMVM_MAX_ORDER + 2) / 2) + kDDThreads - 1) / kDDThreads;
@@ -450,13 +461,14 @@ constexpr int kDDTC = ((MMVM_MAX_ORDER + 1) * ((MMVM_MAX_ORDER + 2) / 2) + kDDTh
 // Each workgroup writes its partial sum over l1 for every k1 of its k2; the
 // emit kernel adds the four partials.  Single vortices only (the interacting
 // path stops far below the double-double orders).
+template <bool CTAB>
 __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs B, StageArgs S)
 {
     const int M = T.M, K = T.K, GM = T.GM, M1 = M + 1;
     const int j = blockIdx.y;
     const int k2 = blockIdx.x >> 2, pass = (blockIdx.x >> 1) & 1, par = blockIdx.x & 1;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const DDShape L(M, par);
+    const DDShape L(M, par, CTAB);
     const int nrp = L.nrp;
     extern __shared__ double smem[];
     double* sS = smem + L.s;
@@ -471,10 +483,10 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
     const int* la = T.dd_la + (long)blockIdx.x * M1 * M1;
     const int* lc = T.dd_lc + (long)blockIdx.x * M1 * H;
     int codeA[kDDTA], codeC[kDDTC];
-    // fills: S rows of parity par, the second-axis factor slice, signed alpha,
-    // binomials and the first-axis diagonals.  Every global load of a thread
-    // is issued before its first LDS store (clamped addresses, zeros selected
-    // afterwards), so the fill costs about one L2 round trip.
+    // fills: S rows of parity par, the band of the second-axis factor slice
+    // and signed alpha.  Every global load of a thread is issued before its
+    // first LDS store (clamped addresses, zeros selected afterwards), so the
+    // fill costs about one L2 round trip.
     {
         constexpr int MM1 = MMVM_MAX_ORDER + 1;
         constexpr int NS = (MM1 * (2 * MMVM_MAX_ORDER + 1) + kDDThreads - 1) / kDDThreads;
@@ -488,7 +500,8 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
         const double* dh = pass == 0 ? T.fd1 : T.fd0;
         const double* dl = pass == 0 ? T.fd1_lo : T.fd0_lo;
         const int nS = nrp * (GM + 1), nQ = M1 * M1, nA = (M1 + 1) * M1;
-        double vsh[NS], vsl[NS], vfh[NQ], vfl[NQ], vbn[NQ], vdh[NQ], vdl[NQ], va[NA];
+        double vsh[NS], vsl[NS], vfh[NQ], vfl[NQ], va[NA];
+        double vbn[CTAB ? NQ : 1], vdh[CTAB ? NQ : 1], vdl[CTAB ? NQ : 1];
 #pragma unroll
         for (int u = 0; u < kDDTA; ++u) codeA[u] = la[min(tid + u * kDDThreads, M1 * M1 - 1)];
 #pragma unroll
@@ -508,9 +521,11 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             const int ec = e < nQ ? e : 0;
             vfh[u] = fh[ec];
             vfl[u] = fl[ec];
-            vbn[u] = T.binom[ec];
-            vdh[u] = dh[ec];
-            vdl[u] = dl[ec];
+            if constexpr (CTAB) {
+                vbn[u] = T.binom[ec];
+                vdh[u] = dh[ec];
+                vdl[u] = dl[ec];
+            }
         }
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
@@ -533,12 +548,18 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
             const int e = tid + u * kDDThreads;
-            if (e < nQ) {
-                sF[2 * e] = vfh[u];
-                sF[2 * e + 1] = vfl[u];
-                sBin[e] = vbn[u];
-                sFd[2 * e] = vdh[u];
-                sFd[2 * e + 1] = vdl[u];
+            const int l2 = e / M1, i = e - l2 * M1;
+            if (e < nQ && (CTAB || (i <= l2 && i <= k2))) {
+                const int o = CTAB ? e : DDShape::band_off(k2, l2) + i;
+                sF[2 * o] = vfh[u];
+                sF[2 * o + 1] = vfl[u];
+            }
+            if constexpr (CTAB) {
+                if (e < nQ) {
+                    sBin[e] = vbn[u];
+                    sFd[2 * e] = vdh[u];
+                    sFd[2 * e + 1] = vdl[u];
+                }
             }
         }
 #pragma unroll
@@ -561,7 +582,7 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             const int imax = pass == 0 ? (l2 < k2 ? l2 : k2) : (l2 < k2 - 1 ? l2 : k2 - 1);
             const int over = k2 + l2 + off + g1 - GM;  // g2 <= GM - g1  <=>  2i >= over
             const int ilo = over > 0 ? (over + 1) >> 1 : 0;
-            const double* fr = sF + 2 * (l2 * M1);
+            const double* fr = sF + 2 * (CTAB ? l2 * M1 : DDShape::band_off(k2, l2));
             const double* sr = sS + 2 * (DDShape::row_off(M, par, r) + k2 + l2 + off);
             // two independent chains (even and odd i) keep more loads in flight
             Acc2 a{0.0, 0.0}, b{0.0, 0.0};
@@ -631,14 +652,26 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             sY[2 * task + 1] = 0.0;
             continue;
         }
+        // binomials and diagonals: LDS (CTAB) or the L2-resident tables
         Acc2 a{0.0, 0.0};
-        const double* bn = sBin + l1 * M1;
-        const double* fd = sFd + 2 * (k1 * M1);
+        const double* bn = (CTAB ? sBin : T.binom) + l1 * M1;
+        const double* fdh;
+        const double* fdl;
+        int fs;  // stride between hi and lo words, and between entries
+        if constexpr (CTAB) {
+            fdh = sFd + 2 * (k1 * M1);
+            fdl = fdh + 1;
+            fs = 2;
+        } else {
+            fdh = (pass == 0 ? T.fd1 : T.fd0) + k1 * M1;
+            fdl = (pass == 0 ? T.fd1_lo : T.fd0_lo) + k1 * M1;
+            fs = 1;
+        }
         if (pass == 0) {
             const int imax = l1 < k1 - 1 ? l1 : k1 - 1;
             for (int i = 0; i <= imax; ++i) {
                 const int r = (k1 + l1 - 2 * i - 1 - par) >> 1;
-                const dd f = dd_mul_d(dd_make(fd[2 * i], fd[2 * i + 1]), bn[i]);
+                const dd f = dd_mul_d(dd_make(fdh[fs * i], fdl[fs * i]), bn[i]);
                 dot2(a, f.hi, f.lo, sS[2 * (r * M1 + l1)], sS[2 * (r * M1 + l1) + 1]);
             }
             a.s = -a.s;
@@ -648,7 +681,7 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
             const int i0 = k1 + l1 + 1 > GM ? 1 : 0;
             for (int i = i0; i <= imax; ++i) {
                 const int r = (k1 + l1 - 2 * i + 1 - par) >> 1;
-                const dd f = dd_mul_d(dd_make(fd[2 * i], fd[2 * i + 1]), bn[i]);
+                const dd f = dd_mul_d(dd_make(fdh[fs * i], fdl[fs * i]), bn[i]);
                 dot2(a, f.hi, f.lo, sS[2 * (r * M1 + l1)], sS[2 * (r * M1 + l1) + 1]);
             }
         }
@@ -1542,17 +1575,21 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     }
     // single vortices only; the fill is sized for kDDThreads threads and orders <= MMVM_MAX_ORDER
     if (B.interact || !B.s_self_lo || T.M > MMVM_MAX_ORDER) return hipErrorInvalidValue;
-    const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0).total;
+    // the workgroups fit one round at one per CU: stage step C's tables in LDS;
+    // more: the smaller layout, two workgroups per CU
+    const bool ctab = 4 * M1 * B.N <= kDDOneRound;
+    const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0, ctab).total;
+    const void* fn = ctab ? (const void*)k_stage2_dd<true> : (const void*)k_stage2_dd<false>;
     if (shmem > 64 * 1024) {
-        hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_dd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)shmem);
+        hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (ea != hipSuccess) {
             (void)hipGetLastError();
             report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
             return ea;
         }
     }
-    launch_kernel(k_stage2_dd, grid, dim3(kDDThreads), shmem, st, T, B, A);
+    if (ctab) launch_kernel(k_stage2_dd<true>, grid, dim3(kDDThreads), shmem, st, T, B, A);
+    else launch_kernel(k_stage2_dd<false>, grid, dim3(kDDThreads), shmem, st, T, B, A);
     return hipGetLastError();
 }
 
