@@ -37,6 +37,22 @@ def test_exports_every_declared_symbol(mm):
     assert set(names) == set(mm.SYMBOLS)
 
 
+def test_autotune_switch_and_report_without_device(mm):
+    """The tuner's switch and report are host-only: with nothing tuned the
+    report is empty, a NULL buffer only sizes it, a short buffer is rejected."""
+    L = mm.lib()
+    assert L.mmvm_autotune_enable(0) == 0
+    assert L.mmvm_autotune_enable(1) == 0
+    need = ctypes.c_size_t(0)
+    assert L.mmvm_autotune_report(None, ctypes.c_size_t(0), ctypes.byref(need)) == 0
+    assert need.value >= 1
+    if need.value == 1:
+        assert mm.autotune_report() == ""
+    buf = ctypes.create_string_buffer(need.value)
+    assert L.mmvm_autotune_report(buf, ctypes.c_size_t(need.value - 1), ctypes.byref(need)) == -1
+    assert L.mmvm_autotune_report(buf, ctypes.c_size_t(need.value), ctypes.byref(need)) == 0
+
+
 def test_status_strings(mm):
     assert mm.lib().mmvm_status_string(-4) == b"MMVM_EZEROCIRC"
 
