@@ -157,7 +157,11 @@ mmvm_status mmvm_server_destroy(mmvm_server* srv);
  * library is bracketed by HIP events on its stream; mmvm_timing_get waits for
  * them and returns the summed duration and launch count of one kernel
  * ("prep", "self", "pair", "stage2", "emit", "apply", "solo").  Enabling
- * clears the totals.  MMVM_ENOTFOUND if the kernel has not run while enabled. */
+ * clears the totals.  MMVM_ENOTFOUND if the kernel has not run while enabled.
+ * The name "graph" returns, timing on or off, the number of replays of
+ * captured stepping graphs since the process started (total_ms = 0): the
+ * matrix-core stepping path replays a captured two-step graph unless timing
+ * is on or the environment variable MMVM_GRAPHS is 0. */
 mmvm_status mmvm_timing_enable(int32_t on);
 mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches);
 

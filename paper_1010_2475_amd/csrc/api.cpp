@@ -192,17 +192,27 @@ mmvm_status device_tables(int M, const DevTables** out)
 // ---------------------------------------------------------------------------
 // workspaces (per device and stream), grown on demand
 // ---------------------------------------------------------------------------
+void Workspace::drop_graph()
+{
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+    graph_M = graph_N = -1;
+}
+
+// callers synchronise the stream first (queued work may still use the buffer)
 void Workspace::release()
 {
+    drop_graph();
     if (base) (void)hipFree(base);
     base = nullptr;
     bytes = 0;
+    clock = nullptr;
 }
 
 namespace {
 struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
-        sselflo, spair, spad, ystate[2], accd, gpartd, gpart, total;
+        sselflo, spair, spad, ystate[2], accd, gpartd, gpart, clock, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 {
@@ -243,6 +253,7 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
         L.gpartd = add(4 * dense);
     }
     L.gpart = add(sizeof(double) * (size_t)N_ * 4 * K * 2);
+    L.clock = add(sizeof(DevClock));
     L.total = need;
     return L;
 }
@@ -311,6 +322,7 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, bool solo, hipStream
     bufs.gpart = (double*)(b + L.gpart);
     bufs.flag = (int*)(b + L.flag);
     flag_ptr = bufs.flag;
+    clock = (DevClock*)(b + L.clock);
     par_dev = (double*)(b + L.lam0);
     return MMVM_OK;
 }

@@ -25,6 +25,15 @@ struct Workspace {
     double* par_dev = nullptr;       // [2N]: lambda_{j,0}^2, then the viscosity of each vortex
     std::vector<double> par_cache;
     int latched = 0;
+    // captured stepping graph of the matrix-core path (two RK4 steps), reused
+    // while its key (order, batch, dt, buffers) holds; see stepper.cpp
+    DevClock* clock = nullptr;
+    hipStream_t cap_stream = nullptr;  // where the graph is captured
+    hipGraphExec_t graph = nullptr;
+    int graph_M = -1, graph_N = -1;
+    double graph_dt = 0.0;
+    const void* graph_tables = nullptr;
+    void drop_graph();
 
     // solo: the vortices do not interact (N = 1, or a batch of independent solves)
     mmvm_status ensure(int N, int M, bool need_dd, bool solo, hipStream_t st);
@@ -32,7 +41,11 @@ struct Workspace {
     // lambda0 [N]; viscosity nu[N], or the scalar nu0 for every vortex when nu is null
     mmvm_status set_params(const double* lambda0, const double* nu, double nu0, int N, hipStream_t st);
     void release();
-    ~Workspace() { release(); }
+    ~Workspace()
+    {
+        release();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 mmvm_status device_tables(int M, const DevTables** out);
@@ -41,6 +54,9 @@ mmvm_status device_tables(int M, const DevTables** out);
 bool timing_on();
 void* timing_begin(hipStream_t st);
 void timing_end(void* tok, const char* name, hipStream_t st);
+// replays of captured stepping graphs since the process started
+void count_graph_replays(int64_t n);
+int64_t graph_replays();
 Workspace* workspace_for(hipStream_t st);
 mmvm_status validate(const mmvm_problem* prob);
 bool use_dd(int M, mmvm_precision prec);

@@ -813,6 +813,9 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     const double* gW = T.wpad + ((long)k2 * 2 + pass) * KA * LP;
     const double* gA = B.alphaS[S.cur] + (long)j * LP * LP;
     const double* gD = pass == 0 ? T.fd1 : T.fd0;
+    // graph replay: the last stage of the captured steps advances the clock
+    // (every reader of it, a self kernel, has finished; the next one starts after)
+    if (S.clock_bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) S.clock_bump->n += 2;
 
     // T is zero except the rows of this parity written after (B)
     {
@@ -987,8 +990,16 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         }
         __shared__ double pw[2][MMVM_MAX_ORDER + 1];  // lambda_prev^s / lambda_prev^2, lambda_next^{-s}
         if (tid <= M) {
-            const double lam2p = l0sq + 4.0 * nuj * P.t_prev;
-            const double lam2n = l0sq + 4.0 * nuj * P.t_next;
+            double tp = P.t_prev, tn = P.t_next;
+            if (P.clock) {
+                // t0 + (n + c) dt as the host evaluates it: separate roundings, no fused multiply-add
+                const double t0 = P.clock->t0;
+                const long long n = P.clock->n;
+                tp = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_prev), P.c_prev), P.dt));
+                tn = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_next), P.c_next), P.dt));
+            }
+            const double lam2p = l0sq + 4.0 * nuj * tp;
+            const double lam2n = l0sq + 4.0 * nuj * tn;
             pw[0][tid] = pow_uint(sqrt(lam2p), tid) / lam2p;
             pw[1][tid] = pow_uint(1.0 / sqrt(lam2n), tid);
             if (writer && par == 0 && tid == 0) B.lam2[cur][j] = lam2n;
@@ -1100,6 +1111,20 @@ __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, 
         const double val = k == 0 ? 0.0 : (T.c1d[k1 * LP + k2] * g) * lp;
         P.mom_out[(long)j * K + k] = B.ystate[P.ycur][o] + P.dt * (B.accD[o] + (1.0 / 6.0) * val);
     }
+}
+
+__global__ void k_set_clock(DevClock* clock, double t0, long long n)
+{
+    if (threadIdx.x == 0) {
+        clock->t0 = t0;
+        clock->n = n;
+    }
+}
+
+hipError_t launch_set_clock(DevClock* clock, double t0, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, st, clock, t0, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st)
@@ -1561,14 +1586,14 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     if (!use_dd) {
         if (!stage2_uses_mfma(T.M, use_dd, !B.interact) || B.interact) return hipErrorInvalidValue;
         const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
-        if (shmem > 64 * 1024) {
-            hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_mfma,
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-            if (ea != hipSuccess) {
-                (void)hipGetLastError();
-                report_hip_error(ea, "hipFuncSetAttribute(k_stage2_mfma dynamic LDS)");
-                return ea;
-            }
+        // the attribute is set to the largest order's size once, so that no
+        // launch (possibly captured into a graph) makes the call
+        static const hipError_t ea = hipFuncSetAttribute(
+            (const void*)k_stage2_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+            (int)(sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder)));
+        if (ea != hipSuccess || shmem > sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder)) {
+            report_hip_error(ea, "hipFuncSetAttribute(k_stage2_mfma dynamic LDS)");
+            return ea != hipSuccess ? ea : hipErrorInvalidValue;
         }
         launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();

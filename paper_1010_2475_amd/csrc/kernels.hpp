@@ -68,6 +68,12 @@ struct StageBufs {
 
 enum StageMode { MODE_RHS = 0, MODE_RK4 = 1 };
 
+// Device-side clock of a captured stepping graph: the stage times are
+// t0 + (n + c) dt with n = clock.n + a step offset baked into each node.
+struct DevClock {
+    double t0;
+    long long n;
+};
 struct StageArgs {
     int mode;
     int stage;         // RK4 stage 0..3
@@ -82,6 +88,7 @@ struct StageArgs {
     double* mom;       // user moments    [N][K]
     double* dx;        // RHS output      [N][2]
     double* dmom;      // RHS output      [N][K]
+    DevClock* clock_bump;  // graph replay: the matrix-core stage 2 advances clock.n by 2
 };
 
 // prep: stage input (xin, min_) -> lam2[cur], alpha[cur], alphaT[cur]; checks
@@ -103,7 +110,14 @@ struct ApplyArgs {
     double t_next;     // time of stage t + 1
     double dt;
     double* mom_out;   // launch_apply_final: y_{n+1} -> the caller's moments
+    // graph replay: when clock is set, t_prev = t0 + (clock.n + n_prev + c_prev) dt
+    // and t_next likewise (the host's expression, evaluated on the device)
+    const DevClock* clock;
+    int n_prev, n_next;
+    double c_prev, c_next;
 };
+// sets a stepping clock (one thread; a kernel, so it may precede graph replays)
+hipError_t launch_set_clock(DevClock* clock, double t0, long long n, hipStream_t st);
 bool stage2_fuses_emit(int M, bool dd, bool solo);
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st);
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st);

@@ -1,6 +1,7 @@
 // RK4 stepping on the device: nsteps x 4 stages.  The state is read once by
 // the prep kernel; afterwards every stage's last kernel writes the next
 // stage's inputs (double-buffered), so a stage costs its compute kernels only.
+#include <cstdlib>
 #include <cstring>
 
 #include "api_internal.hpp"
@@ -10,47 +11,160 @@ namespace mmvm {
 // One vortex on the matrix-core path: each stage's self kernel first finishes
 // the previous stage (see ApplyArgs); the state alternates between the two
 // ystate buffers and reaches the caller's moments with the last stage.
-static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const StageArgs& A0, double t0, int64_t nsteps,
-                                   hipStream_t st)
+//
+// Steps 1 .. nsteps-1 repeat with period two (the state buffer alternates by
+// step; the stage buffers return to buffer 0 after four stages), so they run
+// as replays of one captured two-step graph when there are enough of them.
+// The replays take their stage times from a device clock (t0, n) that the
+// graph's last node advances by two steps; the graph is kept in the workspace
+// and reused by later calls with the same order, batch and dt.
+static const double kStageC[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
+constexpr int64_t kGraphMinSteps = 8;
+
+// MMVM_GRAPHS=0 in the environment keeps every step on direct launches
+static bool graphs_enabled()
 {
-    static const double cst[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
-    StageArgs A = A0;
+    const char* e = std::getenv("MMVM_GRAPHS");
+    return !(e && e[0] == '0');
+}
+
+// The launches of step n (n >= 1; step 0 starts without a previous stage).
+// With clock set, the stage times come from the device clock: n is then an
+// offset from clock.n, and the last stage 2 advances the clock when bump.
+static hipError_t launch_step(const DevTables& T, Workspace& W, StageArgs A, double t0, int64_t n,
+                              DevClock* clock, bool bump, hipStream_t st)
+{
     ApplyArgs P{};
     P.dt = A.dt;
     int cur = 0;
+    for (int s = 0; s < 4; ++s) {
+        const double ts = t0 + ((double)n + kStageC[s]) * A.dt;
+        const int64_t pn = s == 0 ? n - 1 : n;
+        const int ps = s == 0 ? 3 : s - 1;
+        P.stage = ps;
+        P.t_prev = t0 + ((double)pn + kStageC[ps]) * A.dt;
+        P.t_next = ts;
+        P.clock = clock;
+        P.n_prev = (int)pn;
+        P.n_next = (int)n;
+        P.c_prev = kStageC[ps];
+        P.c_next = kStageC[s];
+        // with a clock, n is relative to an odd clock.n: parities are fixed
+        P.ycur = (int)((clock ? pn + 1 : pn) & 1);
+        void* tk = timing_begin(st);
+        hipError_t e = launch_self_apply(T, W.bufs, cur, P, st);
+        timing_end(tk, "self", st);
+        if (e != hipSuccess) return e;
+        A.stage = s;
+        A.cur = cur;
+        A.t_stage = ts;
+        A.t_next = t0 + ((double)n + kStageC[s + 1]) * A.dt;
+        A.clock_bump = (bump && s == 3) ? clock : nullptr;
+        tk = timing_begin(st);
+        e = launch_stage2(T, W.bufs, A, false, st);
+        timing_end(tk, "stage2", st);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
+    return hipSuccess;
+}
+
+// The workspace's two-step graph for this (order, batch, dt), captured on
+// first use; null if capture is not possible here.
+static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const StageArgs& A, hipStream_t st)
+{
+    if (W.graph && W.graph_M == T.M && W.graph_N == W.bufs.N && W.graph_dt == A.dt && W.graph_tables == &T)
+        return W.graph;
+    if (W.graph) {
+        // an older graph may still be queued on this stream
+        if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
+        W.drop_graph();
+    }
+    // captured on the workspace's own stream (the caller's may be the null
+    // stream, which cannot be captured); nothing runs during a capture, and
+    // the replays go to the caller's stream
+    if (!W.cap_stream && hipStreamCreateWithFlags(&W.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        W.cap_stream = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipStream_t cs = W.cap_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipError_t e = launch_step(T, W, A, 0.0, 0, W.clock, false, cs);
+    if (e == hipSuccess) e = launch_step(T, W, A, 0.0, 1, W.clock, true, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess && ec == hipSuccess && g) {
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) x = nullptr;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!x) return nullptr;
+    W.graph = x;
+    W.graph_M = T.M;
+    W.graph_N = W.bufs.N;
+    W.graph_dt = A.dt;
+    W.graph_tables = &T;
+    return x;
+}
+
+static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const StageArgs& A0, double t0, int64_t nsteps,
+                                   hipStream_t st)
+{
+    StageArgs A = A0;
+    A.clock_bump = nullptr;
     hipError_t e = hipSuccess;
-    for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+    // step 0: its first stage has no previous stage to finish
+    {
+        void* tk = timing_begin(st);
+        e = launch_self(T, W.bufs, 0, false, st);
+        timing_end(tk, "self", st);
+        int cur = 0;
         for (int s = 0; s < 4 && e == hipSuccess; ++s) {
-            const double ts = t0 + ((double)n + cst[s]) * A.dt;
-            void* tk = timing_begin(st);
-            if (n == 0 && s == 0) {
-                e = launch_self(T, W.bufs, cur, false, st);
-            } else {
-                // finish the previous stage: (n, s - 1), or the last stage of step n - 1
-                const int64_t pn = s == 0 ? n - 1 : n;
-                const int ps = s == 0 ? 3 : s - 1;
-                P.stage = ps;
-                P.ycur = (int)(pn & 1);
-                P.t_prev = t0 + ((double)pn + cst[ps]) * A.dt;
-                P.t_next = ts;
+            if (s > 0) {
+                ApplyArgs P{};
+                P.dt = A.dt;
+                P.stage = s - 1;
+                P.ycur = 0;
+                P.t_prev = t0 + (0.0 + kStageC[s - 1]) * A.dt;
+                P.t_next = t0 + (0.0 + kStageC[s]) * A.dt;
+                tk = timing_begin(st);
                 e = launch_self_apply(T, W.bufs, cur, P, st);
+                timing_end(tk, "self", st);
+                if (e != hipSuccess) break;
             }
-            timing_end(tk, "self", st);
-            if (e != hipSuccess) break;
             A.stage = s;
             A.cur = cur;
-            A.t_stage = ts;
-            A.t_next = t0 + ((double)n + cst[s + 1]) * A.dt;
+            A.t_stage = t0 + (0.0 + kStageC[s]) * A.dt;
+            A.t_next = t0 + (0.0 + kStageC[s + 1]) * A.dt;
             tk = timing_begin(st);
             e = launch_stage2(T, W.bufs, A, false, st);
             timing_end(tk, "stage2", st);
             cur ^= 1;
         }
     }
+    int64_t n = 1;
+    if (e == hipSuccess && nsteps - 1 >= kGraphMinSteps && graphs_enabled() && !timing_on() && W.clock) {
+        hipGraphExec_t g = stepping_graph(T, W, A, st);
+        if (g) {
+            const int64_t reps = (nsteps - 1) / 2;
+            e = launch_set_clock(W.clock, t0, 1, st);
+            for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
+            if (e == hipSuccess) count_graph_replays(reps);
+            n += 2 * reps;
+        }
+    }
+    for (; n < nsteps && e == hipSuccess; ++n) e = launch_step(T, W, A, t0, n, nullptr, false, st);
     if (e == hipSuccess) {
+        ApplyArgs P{};
+        P.dt = A.dt;
         P.stage = 3;
         P.ycur = (int)((nsteps - 1) & 1);
-        P.t_prev = t0 + ((double)(nsteps - 1) + cst[3]) * A.dt;
+        P.t_prev = t0 + ((double)(nsteps - 1) + kStageC[3]) * A.dt;
         P.mom_out = A.mom;
         void* tk = timing_begin(st);
         e = launch_apply_final(T, W.bufs, P, st);

@@ -53,6 +53,12 @@ def test_autotune_switch_and_report_without_device(mm):
     assert L.mmvm_autotune_report(buf, ctypes.c_size_t(need.value), ctypes.byref(need)) == 0
 
 
+def test_graph_replay_count_without_device(mm):
+    """The replay counter of captured stepping graphs is readable whatever the
+    timing state; nothing has been replayed in a process without a GPU."""
+    assert mm.timing_get("graph") == (0.0, 0)
+
+
 def test_status_strings(mm):
     assert mm.lib().mmvm_status_string(-4) == b"MMVM_EZEROCIRC"
 

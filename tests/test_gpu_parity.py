@@ -301,6 +301,70 @@ def test_persistent_batch_of_many_uneven_solves(env, orc):
         assert np.array_equal(got[i], m1[0]), i
 
 
+def _step_env(env, w, t0, nsteps, prec, graphs, X=None, Mo=None):
+    torch, mm = env
+    dev = torch.device("cuda:0")
+    X = torch.tensor(w.x, device=dev) if X is None else X
+    Mo = torch.tensor(w.mom, device=dev) if Mo is None else Mo
+    os.environ["MMVM_GRAPHS"] = "1" if graphs else "0"
+    try:
+        print("step M=%d steps=%d prec=%d graphs=%d" % (w.M, nsteps, prec, graphs), flush=True)
+        mm.step(w.M, w.nu, w.lam0, t0, w.dt, nsteps, X, Mo, prec)
+        mm.sync()
+    finally:
+        os.environ.pop("MMVM_GRAPHS", None)
+    return X, Mo
+
+
+@pytest.mark.parametrize("M,prec,nsteps", [(12, 0, 21), (16, 1, 22), (24, 0, 30), (40, 1, 21)])
+def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
+    """Large-order stepping replays a captured two-step graph whose stage
+    times come from a device clock; it must give the bits of direct launches,
+    also when the graph is reused by a second call, with other work between."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.single_random(M=M, Re=700.0, seed=M)
+    w.dt = 2e-3
+    r0 = mm.timing_get("graph")[1]
+    _, m_d = _step_env(env, w, 0.05, nsteps, prec, False)
+    assert mm.timing_get("graph")[1] == r0
+    _, m_g = _step_env(env, w, 0.05, nsteps, prec, True)
+    assert mm.timing_get("graph")[1] == r0 + (nsteps - 1) // 2
+    assert np.array_equal(m_g.cpu().numpy(), m_d.cpu().numpy())
+    # eager work between replays, then a second call continuing the run
+    gpu_rhs(env, w, 0.3, prec)
+    t1 = 0.05 + nsteps * w.dt
+    X_d, m_d2 = _step_env(env, w, t1, nsteps + 3, prec, False, Mo=m_d.clone())
+    X_g, m_g2 = _step_env(env, w, t1, nsteps + 3, prec, True, Mo=m_g.clone())
+    assert np.array_equal(m_g2.cpu().numpy(), m_d2.cpu().numpy())
+    assert np.array_equal(X_g.cpu().numpy(), w.x)
+
+
+def test_graph_replay_batch_matches_direct_launches(env):
+    """A batch of three order-20 solves (own viscosities and cores) stepped
+    through graph replays equals direct launches bit for bit."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    members = [wl.single_random(M=20, Re=Re, seed=s, lam0=l0) for Re, s, l0 in ((200.0, 5, 2.0), (2e3, 6, 1.2),
+                                                                                  (2e4, 7, 0.9))]
+    dev = torch.device("cuda:0")
+    out = []
+    for graphs in (False, True):
+        X = torch.tensor(np.concatenate([w.x for w in members]), device=dev)
+        Mo = torch.tensor(np.concatenate([w.mom for w in members]), device=dev)
+        os.environ["MMVM_GRAPHS"] = "1" if graphs else "0"
+        try:
+            print("step_batch graphs=%d" % graphs, flush=True)
+            mm.step_batch(20, [w.nu for w in members], [w.lam0[0] for w in members], 0.0, 1e-3, 17, X, Mo, 1)
+            mm.sync()
+        finally:
+            os.environ.pop("MMVM_GRAPHS", None)
+        out.append(Mo.cpu().numpy())
+        if graphs:
+            assert mm.timing_get("graph")[1] > 0
+    assert np.array_equal(out[0], out[1])
+
+
 def test_large_order_step_matches_oracle(env, orc):
     """Order 12, two RK4 steps of one vortex against the oracle's RK4."""
     from paper_1010_2475_amd import workloads as wl
