@@ -11,7 +11,7 @@ error against the FP64 oracle on sampled right-hand-side rows.  A served leg
 replays the first requests of the seeded Poisson request stream through the
 solve server and reports p50/p99 latency beside its throughput.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-requests R] [--no-configs]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-requests R] [--serve-slots S] [--no-configs]
        [--no-cpu-baseline] [--no-error] [--copy-calibration]
 """
 import argparse
@@ -86,6 +86,11 @@ def serve_leg(mm, wl, n_req, budget, slots, prec):
     """Replays the first n_req requests of the seeded request stream at their
     arrival times through the solve server; latency = arrival -> result ready."""
     reqs = wl.request_stream(n=n_req)
+    # a server loads the coefficient tables of the orders it serves at startup
+    tp = time.perf_counter()
+    for M in sorted({w.M for _, w in reqs}):
+        mm.prepare(M)
+    prep_s = time.perf_counter() - tp
     srv = mm.Server(budget, slots)
     t0 = time.perf_counter()
     pending = []
@@ -120,7 +125,7 @@ def serve_leg(mm, wl, n_req, budget, slots, prec):
     srv.close()
     window = reqs[-1][0]
     offered = sum(w.N * w.K * w.steps for _, w in reqs)
-    return {"requests": n_req, "hbm_budget_bytes": budget, "slots": slots,
+    return {"requests": n_req, "hbm_budget_bytes": budget, "slots": slots, "tables_prepared_s": prep_s,
             "offered_requests_per_s": n_req / window, "arrival_window_s": window,
             "offered_moment_updates_per_s": offered / window,
             "served_moment_updates_per_s": work / wall, "wall_s": wall, "nonfinite_requests": failed,
@@ -202,6 +207,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip timing the other workloads")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-budget-mb", type=int, default=256)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy (y = 1.0 * x over 256 MiB, five launches), the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes, and exit")
@@ -292,7 +298,7 @@ def main():
 
     if args.serve_requests > 0:
         print("serving %d requests" % args.serve_requests, file=sys.stderr, flush=True)
-        out["serve"] = serve_leg(mm, wl, args.serve_requests, args.serve_budget_mb << 20, 8, mm.MIXED)
+        out["serve"] = serve_leg(mm, wl, args.serve_requests, args.serve_budget_mb << 20, args.serve_slots, mm.MIXED)
         out["serve"]["workload"] = ("first requests of the seeded served stream: Poisson arrivals (mean gap "
                                     "5 ms), half single-particle orders 10-40, half multi-vortex N 16-1024 "
                                     "orders 2-6, 200-2000 RK4 steps, mixed precision")

@@ -86,6 +86,15 @@ typedef struct {
 #define MMVM_TABLE_FACTORS 1
 mmvm_status mmvm_coeffs(int32_t order, int32_t kind, void* out, size_t out_bytes, size_t* needed_bytes);
 
+/* Builds the coefficient tables of one order (the closed forms of H_1/H_2 and
+ * the factor tables of eq:FinalSingleI/II, in double-double) on the host and
+ * copies them to the current device, where every later call of that order
+ * finds them.  Optional: the first call of an order does it by itself, which
+ * puts the one-time build into that call (a served request, a timed loop).
+ * The device copy is waited for on a stream of the library's own, so work in
+ * flight on other streams is not synchronised.  MMVM_EORDER outside 0..40. */
+mmvm_status mmvm_prepare(int32_t order);
+
 /* ---------------------------------------------------------------------------
  * One right-hand side at time t (eq:Final_CrossCoef, eq:xjdot_Final):
  * x[n][2], mom[n][K] in, dx[n][2], dmom[n][K] out.  All four are DEVICE

@@ -35,8 +35,13 @@ struct DevTablesOwner {
 std::mutex g_tab_mu;
 std::map<std::pair<int, int>, std::unique_ptr<DevTablesOwner>> g_dev_tables;
 
+// Tables are copied on a stream of their own and waited for there: a
+// device-wide synchronisation would stall behind every solve in flight (the
+// first request of a new order arrives while others run).
+std::map<int, hipStream_t> g_upload_streams;  // per device, under g_tab_mu
+
 template <typename V>
-const typename V::value_type* upload(DevTablesOwner& o, const V& v, hipError_t& err)
+const typename V::value_type* upload(DevTablesOwner& o, const V& v, hipStream_t us, hipError_t& err)
 {
     typedef typename V::value_type E;
     if (err != hipSuccess) return nullptr;
@@ -46,7 +51,10 @@ const typename V::value_type* upload(DevTablesOwner& o, const V& v, hipError_t& 
     err = hipMalloc(&p, n);
     if (err != hipSuccess) return nullptr;
     o.bufs.push_back(p);
-    if (!v.empty()) err = hipMemcpy(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice);
+    if (!v.empty()) {
+        err = hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, us);
+        if (err == hipSuccess) err = hipStreamSynchronize(us);  // v may be a temporary
+    }
     return (const E*)p;
 }
 
@@ -110,24 +118,30 @@ mmvm_status device_tables(int M, const DevTables** out)
     const Tables& H = get_tables(M);
     std::unique_ptr<DevTablesOwner> o(new DevTablesOwner());
     hipError_t err = hipSuccess;
+    hipStream_t& us = g_upload_streams[dev];
+    if (!us && (err = hipStreamCreateWithFlags(&us, hipStreamNonBlocking)) != hipSuccess) {
+        us = nullptr;
+        report_hip_error(err, "table upload stream");
+        return MMVM_EDEVICE;
+    }
     DevTables& d = o->t;
     d.M = H.M; d.K = H.K; d.P = H.P; d.GM = H.GM; d.KG = H.KG; d.T0N = H.T0N;
-    d.t0_hi = upload(*o, H.t0_hi, err);
-    d.t0_lo = upload(*o, H.t0_lo, err);
-    d.f0_hi = upload(*o, H.f0_hi, err);
-    d.f0_lo = upload(*o, H.f0_lo, err);
-    d.f1_hi = upload(*o, H.f1_hi, err);
-    d.f1_lo = upload(*o, H.f1_lo, err);
-    d.binom = upload(*o, H.binom, err);
-    d.fd0 = upload(*o, H.fd0, err);
-    d.fd1 = upload(*o, H.fd1, err);
-    d.fd0_lo = upload(*o, H.fd0_lo, err);
-    d.fd1_lo = upload(*o, H.fd1_lo, err);
+    d.t0_hi = upload(*o, H.t0_hi, us, err);
+    d.t0_lo = upload(*o, H.t0_lo, us, err);
+    d.f0_hi = upload(*o, H.f0_hi, us, err);
+    d.f0_lo = upload(*o, H.f0_lo, us, err);
+    d.f1_hi = upload(*o, H.f1_hi, us, err);
+    d.f1_lo = upload(*o, H.f1_lo, us, err);
+    d.binom = upload(*o, H.binom, us, err);
+    d.fd0 = upload(*o, H.fd0, us, err);
+    d.fd1 = upload(*o, H.fd1, us, err);
+    d.fd0_lo = upload(*o, H.fd0_lo, us, err);
+    d.fd1_lo = upload(*o, H.fd1_lo, us, err);
     {
         std::vector<int32_t> la, lc;
         if (M > kDDThreshold && M <= MMVM_MAX_ORDER) dd_task_lists(M, la, lc);
-        d.dd_la = upload(*o, la, err);
-        d.dd_lc = upload(*o, lc, err);
+        d.dd_la = upload(*o, la, us, err);
+        d.dd_lc = upload(*o, lc, us, err);
     }
     {
         // zero-padded operands of the matrix-core stage 2 (see S2Shape)
@@ -151,8 +165,8 @@ mmvm_status device_tables(int M, const DevTables** out)
             for (int l = 0; l <= M; ++l)
                 for (int i = 0; i <= l; ++i) cpad[(size_t)l * LP + i] = H.binom[(size_t)l * M1 + i];
         }
-        d.wpad = upload(*o, wpad, err);
-        d.cpad = upload(*o, cpad, err);
+        d.wpad = upload(*o, wpad, us, err);
+        d.cpad = upload(*o, cpad, us, err);
         std::vector<double> t0d;
         if (mfma_order(M)) {
             const T0Shape tz(M);
@@ -160,7 +174,7 @@ mmvm_status device_tables(int M, const DevTables** out)
             for (int a = 0; a <= H.T0N; ++a)
                 for (int b = 0; a + b <= H.T0N; ++b) t0d[(size_t)a * tz.TP + b] = H.t0_hi[tri(a, b)];
         }
-        d.t0d = upload(*o, t0d, err);
+        d.t0d = upload(*o, t0d, us, err);
         std::vector<double> c1d;
         if (mfma_order(M)) {
             const int LP = S2Shape(M, 0).LP;
@@ -168,18 +182,18 @@ mmvm_status device_tables(int M, const DevTables** out)
             for (int k1 = 0; k1 <= M; ++k1)
                 for (int k2 = 0; k1 + k2 <= M; ++k2) c1d[(size_t)k1 * LP + k2] = H.c1_hi[tri(k1, k2)];
         }
-        d.c1d = upload(*o, c1d, err);
+        d.c1d = upload(*o, c1d, us, err);
     }
-    d.c1_hi = upload(*o, H.c1_hi, err);
-    d.c1_lo = upload(*o, H.c1_lo, err);
-    d.kap0 = upload(*o, H.kap0, err);
-    d.kap1 = upload(*o, H.kap1, err);
-    d.hol = upload(*o, H.hol, err);
+    d.c1_hi = upload(*o, H.c1_hi, us, err);
+    d.c1_lo = upload(*o, H.c1_lo, us, err);
+    d.kap0 = upload(*o, H.kap0, us, err);
+    d.kap1 = upload(*o, H.kap1, us, err);
+    d.hol = upload(*o, H.hol, us, err);
     std::vector<double> rcp(128, 0.0);
     for (int i = 1; i < 128; ++i) rcp[i] = 1.0 / (double)i;
-    d.rcp = upload(*o, rcp, err);
-    // the tables are read by kernels on any (possibly non-blocking) stream
-    if (err == hipSuccess) err = hipDeviceSynchronize();
+    d.rcp = upload(*o, rcp, us, err);
+    // every copy has completed (waited for on the upload stream), so kernels on
+    // any stream may read the tables
     if (err != hipSuccess) {
         report_hip_error(err, "table upload");
         return err == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
@@ -197,16 +211,52 @@ void Workspace::drop_graph()
     if (graph) (void)hipGraphExecDestroy(graph);
     graph = nullptr;
     graph_M = graph_N = -1;
+    for (auto& g : retired) {
+        (void)hipGraphExecDestroy(g.first);
+        (void)hipEventDestroy(g.second);
+    }
+    retired.clear();
+}
+
+void Workspace::retire_graph()
+{
+    for (size_t i = 0; i < retired.size();) {
+        if (hipEventQuery(retired[i].second) == hipSuccess) {
+            (void)hipGraphExecDestroy(retired[i].first);
+            (void)hipEventDestroy(retired[i].second);
+            retired.erase(retired.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+    (void)hipGetLastError();
+    if (!graph) return;
+    // the event keeps the last replays' place; a fresh one serves the next graph
+    retired.emplace_back(graph, graph_done);
+    graph = nullptr;
+    graph_done = nullptr;
+    graph_M = graph_N = -1;
 }
 
 // callers synchronise the stream first (queued work may still use the buffer)
 void Workspace::release()
 {
+    // the parameter upload reads par_cache until its event
+    if (par_event) (void)hipEventSynchronize(par_event);
     drop_graph();
     if (base) (void)hipFree(base);
     base = nullptr;
     bytes = 0;
     clock = nullptr;
+    par_cache.clear();
+}
+
+Workspace::~Workspace()
+{
+    release();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (par_event) (void)hipEventDestroy(par_event);
+    if (graph_done) (void)hipEventDestroy(graph_done);
 }
 
 namespace {
@@ -335,11 +385,21 @@ mmvm_status Workspace::set_params(const double* lambda0, const double* nu, doubl
         p[N_ + j] = nu ? nu[j] : nu0;
     }
     if (p == par_cache) return MMVM_OK;
-    // the device copy may be read by queued work; order the update on the stream
-    if (hipMemcpyAsync(par_dev, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    // The device copy may be read by queued work, so the update is ordered on
+    // the stream; its source is the cached host copy, which is replaced only
+    // after the previous update has completed (its event, not the stream).
+    if (par_event && hipEventSynchronize(par_event) != hipSuccess) return MMVM_EDEVICE;
+    if (!par_event && hipEventCreateWithFlags(&par_event, hipEventDisableTiming) != hipSuccess) {
+        par_event = nullptr;
         return MMVM_EDEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) return MMVM_EDEVICE;
+    }
     par_cache.swap(p);
+    if (hipMemcpyAsync(par_dev, par_cache.data(), sizeof(double) * par_cache.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipEventRecord(par_event, st) != hipSuccess) {
+        par_cache.clear();
+        return MMVM_EDEVICE;
+    }
     return MMVM_OK;
 }
 
@@ -486,6 +546,13 @@ mmvm_status mmvm_coeffs(int32_t order, int32_t kind, void* out, size_t out_bytes
         return MMVM_OK;
     }
     return MMVM_EINVAL;
+}
+
+mmvm_status mmvm_prepare(int32_t order)
+{
+    if (order < 0 || order > MMVM_MAX_ORDER) return MMVM_EORDER;
+    const DevTables* T = nullptr;
+    return device_tables(order, &T);
 }
 
 mmvm_status mmvm_rhs(const mmvm_problem* prob, double t, const double* x, const double* mom, double* dx,

@@ -24,16 +24,21 @@ struct Workspace {
     int* flag_ptr = nullptr;
     double* par_dev = nullptr;       // [2N]: lambda_{j,0}^2, then the viscosity of each vortex
     std::vector<double> par_cache;
+    hipEvent_t par_event = nullptr;    // the upload from par_cache has completed
     int latched = 0;
     // captured stepping graph of the matrix-core path (two RK4 steps), reused
     // while its key (order, batch, dt, buffers) holds; see stepper.cpp
     DevClock* clock = nullptr;
     hipStream_t cap_stream = nullptr;  // where the graph is captured
     hipGraphExec_t graph = nullptr;
+    hipEvent_t graph_done = nullptr;   // recorded after the replays of a call
     int graph_M = -1, graph_N = -1;
     double graph_dt = 0.0;
     const void* graph_tables = nullptr;
-    void drop_graph();
+    // graphs replaced while possibly queued, each with an event after its last replays
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
+    void drop_graph();    // the graph is not in flight (the stream was synchronised)
+    void retire_graph();  // the graph may be in flight; also destroys retired ones that finished
 
     // solo: the vortices do not interact (N = 1, or a batch of independent solves)
     mmvm_status ensure(int N, int M, bool need_dd, bool solo, hipStream_t st);
@@ -41,11 +46,7 @@ struct Workspace {
     // lambda0 [N]; viscosity nu[N], or the scalar nu0 for every vortex when nu is null
     mmvm_status set_params(const double* lambda0, const double* nu, double nu0, int N, hipStream_t st);
     void release();
-    ~Workspace()
-    {
-        release();
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    }
+    ~Workspace();
 };
 
 mmvm_status device_tables(int M, const DevTables** out);

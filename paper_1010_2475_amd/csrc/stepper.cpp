@@ -75,11 +75,9 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
 {
     if (W.graph && W.graph_M == T.M && W.graph_N == W.bufs.N && W.graph_dt == A.dt && W.graph_tables == &T)
         return W.graph;
-    if (W.graph) {
-        // an older graph may still be queued on this stream
-        if (hipStreamSynchronize(st) != hipSuccess) return nullptr;
-        W.drop_graph();
-    }
+    // an older graph may still be queued: it is retired behind the event of
+    // its last replays and destroyed once that has fired
+    W.retire_graph();
     // captured on the workspace's own stream (the caller's may be the null
     // stream, which cannot be captured); nothing runs during a capture, and
     // the replays go to the caller's stream
@@ -104,6 +102,11 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();
     if (!x) return nullptr;
+    if (!W.graph_done && hipEventCreateWithFlags(&W.graph_done, hipEventDisableTiming) != hipSuccess) {
+        W.graph_done = nullptr;
+        (void)hipGraphExecDestroy(x);
+        return nullptr;
+    }
     W.graph = x;
     W.graph_M = T.M;
     W.graph_N = W.bufs.N;
@@ -154,6 +157,7 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
             const int64_t reps = (nsteps - 1) / 2;
             e = launch_set_clock(W.clock, t0, 1, st);
             for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
+            if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
             if (e == hipSuccess) count_graph_replays(reps);
             n += 2 * reps;
         }

@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
 
 _lib = None
 
-SYMBOLS = ["mmvm_coeffs", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
+SYMBOLS = ["mmvm_coeffs", "mmvm_prepare", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
            "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
            "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_status_string"]
 
@@ -64,6 +64,7 @@ def lib():
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(Problem)
     L.mmvm_coeffs.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.mmvm_prepare.argtypes = [ctypes.c_int32]
     L.mmvm_rhs.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
     L.mmvm_step.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
     L.mmvm_step_batch.argtypes = [ctypes.POINTER(Batch), ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp,
@@ -138,6 +139,11 @@ def rhs(M, nu, lambda0, t, x, mom, dx, dmom, prec=FP64, stream=None):
     _check(lib().mmvm_rhs(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
                           _dev(dx, (N, 2), "dx"), _dev(dmom, (N, K), "dmom"), int(prec), _stream(stream)),
            "mmvm_rhs")
+
+
+def prepare(M):
+    """Builds the tables of order M on the current device (mmvm_prepare)."""
+    _check(lib().mmvm_prepare(int(M)), "mmvm_prepare")
 
 
 def step(M, nu, lambda0, t0, dt, nsteps, x, mom, prec=FP64, stream=None):

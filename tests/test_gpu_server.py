@@ -64,6 +64,22 @@ def test_same_alone_and_in_the_mix(mm, prec):
     srv.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reused_buffers_do_not_change_results(mm, prec):
+    """One slot: every request after the first runs in the workspace, device
+    buffer and pinned buffer that an earlier request of another shape left in
+    the server's pools; results equal solving each alone in a fresh server."""
+    reqs = _requests()[::-1] + _requests()
+    alone = [_solve_alone(mm, w, prec) for w in reqs]
+    srv = mm.Server(1 << 30, 1)
+    tickets = [srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, prec) for w in reqs]
+    srv.drain()
+    for i, (w, tk, (xa, ma, _)) in enumerate(zip(reqs, tickets, alone)):
+        x, m, st = srv.poll(tk, w.N, w.M)
+        assert np.array_equal(x, xa) and np.array_equal(m, ma), i
+    srv.close()
+
+
 def test_server_matches_direct_stepping(mm):
     import torch
     from paper_1010_2475_amd import workloads as wl
