@@ -62,12 +62,12 @@ def self_flops(M):
 # from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
-# and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262149 KiB).
+# and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3271.2, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
-                  "write_scale": 262144.0 / 262149.0,
-                  "sources_sha256": {"kernels.hip": "65d763ab95384107b1dcfb4fc1a980f973d67c03634a7f48f14ac9668634a8d8",
-                                     "kernels.hpp": "0fdb691c5dbc198f8703be09f0e6c2ef2a333c3ed8210e6ead5819cd231b6df0"}}
+TRAFFIC_STAGE2 = {"fetch_kib": 3272.4, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
+                  "write_scale": 262144.0 / 262146.0,
+                  "sources_sha256": {"kernels.hip": "91f85b28345160f9266f0b8be38365cbec673eee79ee819fad2521e3c1bf287a",
+                                     "kernels.hpp": "19cf92c996389e0eb7d506e1b9f3e1d9c3632fea8e189f5b8072056a7a8b4cde"}}
 
 
 def stage2_traffic_bytes():
