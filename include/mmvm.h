@@ -168,9 +168,10 @@ mmvm_status mmvm_server_destroy(mmvm_server* srv);
  * ("prep", "self", "pair", "stage2", "emit", "apply", "solo").  Enabling
  * clears the totals.  MMVM_ENOTFOUND if the kernel has not run while enabled.
  * The name "graph" returns, timing on or off, the number of replays of
- * captured stepping graphs since the process started (total_ms = 0): the
- * matrix-core stepping path replays a captured two-step graph unless timing
- * is on or the environment variable MMVM_GRAPHS is 0. */
+ * captured stepping graphs since the process started (total_ms = 0): calls
+ * of at least 9 steps on the large-order paths replay a captured graph (two
+ * steps on the matrix-core path, one step on the double-double path) unless
+ * timing is on or the environment variable MMVM_GRAPHS is 0. */
 mmvm_status mmvm_timing_enable(int32_t on);
 mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches);
 

@@ -210,7 +210,7 @@ void Workspace::drop_graph()
 {
     if (graph) (void)hipGraphExecDestroy(graph);
     graph = nullptr;
-    graph_M = graph_N = -1;
+    graph_kind = graph_M = graph_N = -1;
     for (auto& g : retired) {
         (void)hipGraphExecDestroy(g.first);
         (void)hipEventDestroy(g.second);
@@ -235,7 +235,7 @@ void Workspace::retire_graph()
     retired.emplace_back(graph, graph_done);
     graph = nullptr;
     graph_done = nullptr;
-    graph_M = graph_N = -1;
+    graph_kind = graph_M = graph_N = -1;
 }
 
 // callers synchronise the stream first (queued work may still use the buffer)

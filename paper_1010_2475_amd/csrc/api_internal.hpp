@@ -26,15 +26,18 @@ struct Workspace {
     std::vector<double> par_cache;
     hipEvent_t par_event = nullptr;    // the upload from par_cache has completed
     int latched = 0;
-    // captured stepping graph of the matrix-core path (two RK4 steps), reused
-    // while its key (order, batch, dt, buffers) holds; see stepper.cpp
+    // captured stepping graph (two RK4 steps of the matrix-core path, or one of
+    // the double-double path), reused while its key (kind, order, batch, dt,
+    // tables, the caller's state for the double-double path) holds; see stepper.cpp
     DevClock* clock = nullptr;
     hipStream_t cap_stream = nullptr;  // where the graph is captured
     hipGraphExec_t graph = nullptr;
     hipEvent_t graph_done = nullptr;   // recorded after the replays of a call
-    int graph_M = -1, graph_N = -1;
+    int graph_kind = -1, graph_M = -1, graph_N = -1;
     double graph_dt = 0.0;
     const void* graph_tables = nullptr;
+    const void* graph_x = nullptr;
+    const void* graph_mom = nullptr;
     // graphs replaced while possibly queued, each with an event after its last replays
     std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
     void drop_graph();    // the graph is not in flight (the stream was synchronised)

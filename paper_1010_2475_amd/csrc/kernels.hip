@@ -237,8 +237,11 @@ template <bool DD>
 __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int KG, int T0N,
                                               const double* __restrict__ alpha, const double* __restrict__ t0h,
                                               const double* __restrict__ t0l, double* __restrict__ sself,
-                                              double* __restrict__ sself_lo)
+                                              double* __restrict__ sself_lo, DevClock* bump)
 {
+    // graph replay: the first kernel of a replayed step advances its clock (no
+    // kernel of the step has read it yet; they all run after this one)
+    if (bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) bump->n += 1;
     // LDS: alpha of the vortex [K] and the Psi0 table [tri(T0N)] (hi, lo).
     // Four lanes share one entry g, each summing every fourth even-step m2.
     extern __shared__ double sm_self[];
@@ -301,19 +304,19 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
     }
 }
 
-hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st)
+hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st, DevClock* bump)
 {
-    if (stage2_uses_mfma(T.M, dd, !B.interact)) return launch_self_pad(T, B, cur, st);
+    if (stage2_uses_mfma(T.M, dd, !B.interact)) return bump ? hipErrorInvalidValue : launch_self_pad(T, B, cur, st);
     const int threads = 256;
     dim3 grid(((dd ? 8 : 4) * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
     size_t shmem = sizeof(double) * ((size_t)T.K + (dd ? 2 : 1) * (size_t)nt0);
     if (dd)
         launch_kernel(k_self<true>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
-                           B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, B.s_self_lo);
+                           B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, B.s_self_lo, bump);
     else
         launch_kernel(k_self<false>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
-                           B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, (double*)nullptr);
+                           B.alpha[cur], T.t0_hi, T.t0_lo, B.s_self, (double*)nullptr, bump);
     return hipGetLastError();
 }
 
@@ -1155,7 +1158,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
     const double* sp = B.interact ? B.s_pair + (long)j * T.KG : nullptr;
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
+    double tn = S.t_next;
+    if (S.clock)  // as the host evaluates t0 + (n + c) dt: separate roundings
+        tn = __dadd_rn(S.clock->t0, __dmul_rn(__dadd_rn((double)(S.clock->n + S.n_rel), S.c_next), S.dt));
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * tn;
     double xd1 = 0.0, xd2 = 0.0;
     if (B.interact) centre_velocity(al, sp, K, lam, red, xd1, xd2);
     const double* gj = B.gpart + (long)j * 4 * K * 2;
@@ -1604,14 +1610,18 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     // more: the smaller layout, two workgroups per CU
     const bool ctab = 4 * M1 * B.N <= kDDOneRound;
     const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0, ctab).total;
-    const void* fn = ctab ? (const void*)k_stage2_dd<true> : (const void*)k_stage2_dd<false>;
-    if (shmem > 64 * 1024) {
-        hipError_t ea = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (ea != hipSuccess) {
-            (void)hipGetLastError();
-            report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
-            return ea;
-        }
+    // each variant's attribute is set once, to the largest order's size (no
+    // launch, possibly captured into a graph, makes the call)
+    static const hipError_t ea_t = hipFuncSetAttribute(
+        (const void*)k_stage2_dd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(sizeof(double) * (size_t)DDShape(MMVM_MAX_ORDER, 0, true).total));
+    static const hipError_t ea_f = hipFuncSetAttribute(
+        (const void*)k_stage2_dd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(sizeof(double) * (size_t)DDShape(MMVM_MAX_ORDER, 0, false).total));
+    const hipError_t ea = ctab ? ea_t : ea_f;
+    if (ea != hipSuccess) {
+        report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
+        return ea;
     }
     if (ctab) launch_kernel(k_stage2_dd<true>, grid, dim3(kDDThreads), shmem, st, T, B, A);
     else launch_kernel(k_stage2_dd<false>, grid, dim3(kDDThreads), shmem, st, T, B, A);

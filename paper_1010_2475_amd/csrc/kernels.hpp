@@ -89,14 +89,22 @@ struct StageArgs {
     double* dx;        // RHS output      [N][2]
     double* dmom;      // RHS output      [N][K]
     DevClock* clock_bump;  // graph replay: the matrix-core stage 2 advances clock.n by 2
+    // graph replay of the double-double path: when clock is set the emit
+    // kernel takes t_next = t0 + (clock.n + n_rel + c_next) dt (the step's
+    // first self kernel advances clock.n, see launch_self)
+    const DevClock* clock;
+    int n_rel;
+    double c_next;
 };
 
 // prep: stage input (xin, min_) -> lam2[cur], alpha[cur], alphaT[cur]; checks
 // circulation/finiteness; copies the state into (xs, ys) when they differ
 hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
                        double t, bool need_pair, bool need_f32, hipStream_t st);
-// self velocity-derivative table (orders without a fused self term); dd = double-double
-hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st);
+// self velocity-derivative table (orders without a fused self term); dd = double-double.
+// bump (graph replay): the kernel first advances bump->n by one
+hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st,
+                       DevClock* bump = nullptr);
 
 // Matrix-core RK4 stepping of one vortex: the self kernel of stage t + 1 first
 // finishes stage t from its partial contractions (RK4 update of the state held

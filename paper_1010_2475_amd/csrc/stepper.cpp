@@ -69,11 +69,40 @@ static hipError_t launch_step(const DevTables& T, Workspace& W, StageArgs A, dou
     return hipSuccess;
 }
 
-// The workspace's two-step graph for this (order, batch, dt), captured on
-// first use; null if capture is not possible here.
-static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const StageArgs& A, hipStream_t st)
+// One step of the double-double path (self, stage 2 and emit kernels of each
+// stage; the stage buffers return to buffer 0 after the four stages) with its
+// stage times taken from the device clock: the step's first kernel advances
+// clock.n by one, and the emit kernels, the only ones that read a time, come
+// after it.  The emits update the caller's state (A.x, A.mom) in place.
+static hipError_t launch_dd_step(const DevTables& T, Workspace& W, StageArgs A, hipStream_t st)
 {
-    if (W.graph && W.graph_M == T.M && W.graph_N == W.bufs.N && W.graph_dt == A.dt && W.graph_tables == &T)
+    int cur = 0;
+    for (int s = 0; s < 4; ++s) {
+        A.stage = s;
+        A.cur = cur;
+        A.clock = W.clock;
+        A.n_rel = 0;
+        A.c_next = kStageC[s + 1];
+        hipError_t e = launch_self(T, W.bufs, cur, true, st, s == 0 ? W.clock : nullptr);
+        if (e == hipSuccess) e = launch_stage2(T, W.bufs, A, true, st);
+        if (e == hipSuccess) e = launch_emit(T, W.bufs, A, true, st);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
+    return hipSuccess;
+}
+
+enum { kGraphMFMA = 0, kGraphDD = 1 };
+
+// The workspace's stepping graph of this kind for this (order, batch, dt, and
+// for the double-double path the caller's state), captured on first use; null
+// if capture is not possible here.
+static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const StageArgs& A, int kind, hipStream_t st)
+{
+    const void* gx = kind == kGraphDD ? (const void*)A.x : nullptr;
+    const void* gm = kind == kGraphDD ? (const void*)A.mom : nullptr;
+    if (W.graph && W.graph_kind == kind && W.graph_M == T.M && W.graph_N == W.bufs.N && W.graph_dt == A.dt &&
+        W.graph_tables == &T && W.graph_x == gx && W.graph_mom == gm)
         return W.graph;
     // an older graph may still be queued: it is retired behind the event of
     // its last replays and destroyed once that has fired
@@ -91,8 +120,13 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
         (void)hipGetLastError();
         return nullptr;
     }
-    hipError_t e = launch_step(T, W, A, 0.0, 0, W.clock, false, cs);
-    if (e == hipSuccess) e = launch_step(T, W, A, 0.0, 1, W.clock, true, cs);
+    hipError_t e;
+    if (kind == kGraphDD) {
+        e = launch_dd_step(T, W, A, cs);
+    } else {
+        e = launch_step(T, W, A, 0.0, 0, W.clock, false, cs);
+        if (e == hipSuccess) e = launch_step(T, W, A, 0.0, 1, W.clock, true, cs);
+    }
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
     hipGraphExec_t x = nullptr;
@@ -108,6 +142,9 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
         return nullptr;
     }
     W.graph = x;
+    W.graph_kind = kind;
+    W.graph_x = gx;
+    W.graph_mom = gm;
     W.graph_M = T.M;
     W.graph_N = W.bufs.N;
     W.graph_dt = A.dt;
@@ -152,7 +189,7 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
     }
     int64_t n = 1;
     if (e == hipSuccess && nsteps - 1 >= kGraphMinSteps && graphs_enabled() && !timing_on() && W.clock) {
-        hipGraphExec_t g = stepping_graph(T, W, A, st);
+        hipGraphExec_t g = stepping_graph(T, W, A, kGraphMFMA, st);
         if (g) {
             const int64_t reps = (nsteps - 1) / 2;
             e = launch_set_clock(W.clock, t0, 1, st);
@@ -208,7 +245,25 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, in
     mmvm_status r = run_prep(T, W, cur, x, mom, t0, prec, st);
     if (r != MMVM_OK) return r;
     if (stage2_fuses_emit(T.M, use_dd(T.M, prec), !W.bufs.interact)) return run_steps_fused(T, W, A, t0, nsteps, st);
+    // the double-double path (single vortices): step 0 direct, the rest as
+    // replays of a one-step graph on a clock that starts at step 0
+    const bool dd_graph = use_dd(T.M, prec) && !W.bufs.interact && nsteps - 1 >= kGraphMinSteps &&
+                          graphs_enabled() && !timing_on() && W.clock;
     for (int64_t n = 0; n < nsteps; ++n) {
+        if (n == 1 && dd_graph) {
+            hipGraphExec_t g = stepping_graph(T, W, A, kGraphDD, st);
+            if (g) {
+                hipError_t e = launch_set_clock(W.clock, t0, 0, st);
+                for (int64_t r = 1; r < nsteps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
+                if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
+                if (e != hipSuccess) {
+                    report_hip_error(e, "stepping graph replay");
+                    return MMVM_EDEVICE;
+                }
+                count_graph_replays(nsteps - 1);
+                return MMVM_OK;
+            }
+        }
         for (int s = 0; s < 4; ++s) {
             A.stage = s;
             A.cur = cur;

@@ -316,20 +316,25 @@ def _step_env(env, w, t0, nsteps, prec, graphs, X=None, Mo=None):
     return X, Mo
 
 
-@pytest.mark.parametrize("M,prec,nsteps", [(12, 0, 21), (16, 1, 22), (24, 0, 30), (40, 1, 21)])
+@pytest.mark.parametrize("M,prec,nsteps", [(12, 0, 21), (16, 1, 22), (24, 0, 30), (40, 1, 21), (30, 0, 21),
+                                           (40, 0, 12)])
 def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
-    """Large-order stepping replays a captured two-step graph whose stage
-    times come from a device clock; it must give the bits of direct launches,
-    also when the graph is reused by a second call, with other work between."""
+    """Large-order stepping replays a captured graph (two steps on the matrix
+    cores; one step of the double-double path, FP64 above order 24) whose
+    stage times come from a device clock; it must give the bits of direct
+    launches, also when a second call recaptures it for other state buffers,
+    with other work between, and when a third call reuses it."""
     torch, mm = env
     from paper_1010_2475_amd import workloads as wl
     w = wl.single_random(M=M, Re=700.0, seed=M)
     w.dt = 2e-3
+    dd = prec == 0 and M > 24
+    reps = (nsteps - 1) if dd else (nsteps - 1) // 2
     r0 = mm.timing_get("graph")[1]
     _, m_d = _step_env(env, w, 0.05, nsteps, prec, False)
     assert mm.timing_get("graph")[1] == r0
     _, m_g = _step_env(env, w, 0.05, nsteps, prec, True)
-    assert mm.timing_get("graph")[1] == r0 + (nsteps - 1) // 2
+    assert mm.timing_get("graph")[1] == r0 + reps
     assert np.array_equal(m_g.cpu().numpy(), m_d.cpu().numpy())
     # eager work between replays, then a second call continuing the run
     gpu_rhs(env, w, 0.3, prec)
@@ -338,15 +343,21 @@ def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
     X_g, m_g2 = _step_env(env, w, t1, nsteps + 3, prec, True, Mo=m_g.clone())
     assert np.array_equal(m_g2.cpu().numpy(), m_d2.cpu().numpy())
     assert np.array_equal(X_g.cpu().numpy(), w.x)
+    # a third call on the same buffers (the graph is reused; the clock restarts)
+    t2 = t1 + (nsteps + 3) * w.dt
+    _step_env(env, w, t2, nsteps, prec, False, X=X_d, Mo=m_d2)
+    _step_env(env, w, t2, nsteps, prec, True, X=X_g, Mo=m_g2)
+    assert np.array_equal(m_g2.cpu().numpy(), m_d2.cpu().numpy())
 
 
-def test_graph_replay_batch_matches_direct_launches(env):
-    """A batch of three order-20 solves (own viscosities and cores) stepped
-    through graph replays equals direct launches bit for bit."""
+@pytest.mark.parametrize("M,prec", [(20, 1), (32, 0)])
+def test_graph_replay_batch_matches_direct_launches(env, M, prec):
+    """A batch of three solves (own viscosities and cores) stepped through
+    graph replays equals direct launches bit for bit."""
     torch, mm = env
     from paper_1010_2475_amd import workloads as wl
-    members = [wl.single_random(M=20, Re=Re, seed=s, lam0=l0) for Re, s, l0 in ((200.0, 5, 2.0), (2e3, 6, 1.2),
-                                                                                  (2e4, 7, 0.9))]
+    members = [wl.single_random(M=M, Re=Re, seed=s, lam0=l0) for Re, s, l0 in ((200.0, 5, 2.0), (2e3, 6, 1.2),
+                                                                                 (2e4, 7, 0.9))]
     dev = torch.device("cuda:0")
     out = []
     for graphs in (False, True):
@@ -355,7 +366,7 @@ def test_graph_replay_batch_matches_direct_launches(env):
         os.environ["MMVM_GRAPHS"] = "1" if graphs else "0"
         try:
             print("step_batch graphs=%d" % graphs, flush=True)
-            mm.step_batch(20, [w.nu for w in members], [w.lam0[0] for w in members], 0.0, 1e-3, 17, X, Mo, 1)
+            mm.step_batch(M, [w.nu for w in members], [w.lam0[0] for w in members], 0.0, 1e-3, 17, X, Mo, prec)
             mm.sync()
         finally:
             os.environ.pop("MMVM_GRAPHS", None)
