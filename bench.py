@@ -9,7 +9,8 @@ step of all three solves (stepped together as one batch of independent solves). 
 path (value) and the strict FP64 path (reported beside it), each with its
 error against the FP64 oracle on sampled right-hand-side rows.  A served leg
 replays the first requests of the seeded Poisson request stream through the
-solve server and reports p50/p99 latency beside its throughput.
+solve server and reports p50/p99 latency beside its throughput, at the stream's
+own rate and at 1/20 of it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve-requests R] [--serve-slots S] [--no-configs]
        [--no-cpu-baseline] [--no-error] [--copy-calibration]
@@ -64,10 +65,10 @@ def self_flops(M):
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
 # and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3272.4, "write_kib": 169.1, "fetch_scale": 262144.0 / 131083.0,
-                  "write_scale": 262144.0 / 262146.0,
-                  "sources_sha256": {"kernels.hip": "91f85b28345160f9266f0b8be38365cbec673eee79ee819fad2521e3c1bf287a",
-                                     "kernels.hpp": "19cf92c996389e0eb7d506e1b9f3e1d9c3632fea8e189f5b8072056a7a8b4cde"}}
+TRAFFIC_STAGE2 = {"fetch_kib": 3272.4, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.6,
+                  "write_scale": 262144.0 / 262146.3,
+                  "sources_sha256": {"kernels.hip": "83c251f5e838b105b96f0c44b453920fcf060f7bb83a48a8f93392d0d6bbf39d",
+                                     "kernels.hpp": "3375d55249804302b7f19d77820bd8e2815f2cb4916c061604557fc53805903d"}}
 
 
 def stage2_traffic_bytes():
@@ -82,10 +83,11 @@ def stage2_traffic_bytes():
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
-def serve_leg(mm, wl, n_req, budget, slots, prec):
+def serve_leg(mm, wl, n_req, budget, slots, prec, stretch=1.0):
     """Replays the first n_req requests of the seeded request stream at their
-    arrival times through the solve server; latency = arrival -> result ready."""
-    reqs = wl.request_stream(n=n_req)
+    arrival times (multiplied by stretch) through the solve server; latency =
+    arrival -> result ready."""
+    reqs = [(ta * stretch, w) for ta, w in wl.request_stream(n=n_req)]
     # a server loads the coefficient tables of the orders it serves at startup
     tp = time.perf_counter()
     for M in sorted({w.M for _, w in reqs}):
@@ -302,6 +304,11 @@ def main():
         out["serve"]["workload"] = ("first requests of the seeded served stream: Poisson arrivals (mean gap "
                                     "5 ms), half single-particle orders 10-40, half multi-vortex N 16-1024 "
                                     "orders 2-6, 200-2000 RK4 steps, mixed precision")
+        # the same requests at 1/20 of the arrival rate, a load one GPU keeps up with
+        print("serving %d requests at 1/20 of the rate" % args.serve_requests, file=sys.stderr, flush=True)
+        out["serve_light"] = serve_leg(mm, wl, args.serve_requests, args.serve_budget_mb << 20, args.serve_slots,
+                                       mm.MIXED, stretch=20.0)
+        out["serve_light"]["workload"] = "the same requests with arrival times stretched 20x (mean gap 100 ms)"
 
     if not args.no_error or not args.no_cpu_baseline:
         import oracle
