@@ -12,6 +12,8 @@
 // All quantities are in "lambda units" of the target vortex: with
 // alpha_l = M_l lambda^{-|l|} and S in units lambda^{|g|}, eq:moment_evolutionFinish
 // becomes dM_k/dt = lambda^{|k|-2} G_k(alpha, S) with lambda-free tables.
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -21,6 +23,30 @@
 #include "util.hpp"
 
 namespace mmvm {
+
+// Raises a kernel's dynamic-LDS limit to `bytes`, once per (kernel, device): the
+// runtime keeps the attribute per device.  Later calls only look the result
+// up, so a launch that a caller captures into a graph makes no attribute call
+// once an uncaptured launch on that device has made it.
+static hipError_t lds_limit_once(const void* fn, size_t bytes, const char* what)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, hipError_t> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(fn, dev);
+    auto it = done.find(key);
+    if (it != done.end()) return it->second;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        report_hip_error(e, what);
+    }
+    done[key] = e;
+    return e;
+}
 
 // ---------------------------------------------------------------------------
 // prep
@@ -233,8 +259,13 @@ __device__ __forceinline__ void acc2_merge(Acc2& a, const Acc2& b)
 // the accumulated value as a normalised double-double
 __device__ __forceinline__ dd acc2_value(const Acc2& a) { return two_sum(a.s, a.c); }
 
+constexpr int kSelfVThreads = 256;  // workgroup size of k_self
+constexpr int kSelfFillA = ((MMVM_MAX_ORDER + 1) * (MMVM_MAX_ORDER + 2) / 2 + kSelfVThreads - 1) / kSelfVThreads;
+constexpr int kSelfT0NMax = (3 * MMVM_MAX_ORDER + 1) / 2 + 1;
+constexpr int kSelfFillT = ((kSelfT0NMax + 1) * (kSelfT0NMax + 2) / 2 + kSelfVThreads - 1) / kSelfVThreads;
+
 template <bool DD>
-__global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int KG, int T0N,
+__global__ __launch_bounds__(kSelfVThreads) void k_self(int N, int M, int K, int GM, int KG, int T0N,
                                               const double* __restrict__ alpha, const double* __restrict__ t0h,
                                               const double* __restrict__ t0l, double* __restrict__ sself,
                                               double* __restrict__ sself_lo, DevClock* bump)
@@ -251,15 +282,35 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
     double* tl = th + nt0;
     const int j = blockIdx.y;
     const double* a = alpha + (long)j * K;
-    for (int i = threadIdx.x; i < K; i += blockDim.x) sa[i] = a[i];
-    for (int i = threadIdx.x; i < nt0; i += blockDim.x) {
-        th[i] = t0h[i];
-        if (DD) tl[i] = t0l[i];
+    {
+        // every load is issued before the first LDS store (indices clamped
+        // into the arrays; the stores past their ends are skipped)
+        const int tid = threadIdx.x;
+        double va[kSelfFillA], vh[kSelfFillT], vl[kSelfFillT];
+#pragma unroll
+        for (int u = 0; u < kSelfFillA; ++u) va[u] = a[min(tid + u * kSelfVThreads, K - 1)];
+#pragma unroll
+        for (int u = 0; u < kSelfFillT; ++u) {
+            const int i = min(tid + u * kSelfVThreads, nt0 - 1);
+            vh[u] = t0h[i];
+            if constexpr (DD) vl[u] = t0l[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kSelfFillA; ++u)
+            if (tid + u * kSelfVThreads < K) sa[tid + u * kSelfVThreads] = va[u];
+#pragma unroll
+        for (int u = 0; u < kSelfFillT; ++u) {
+            const int i = tid + u * kSelfVThreads;
+            if (i < nt0) {
+                th[i] = vh[u];
+                if constexpr (DD) tl[i] = vl[u];
+            }
+        }
     }
     __syncthreads();
     // four lanes share one entry g (eight for the compensated sums)
     constexpr int LANES = DD ? 8 : 4;
-    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gt = blockIdx.x * kSelfVThreads + threadIdx.x;
     const int g = gt / LANES, q = gt % LANES;
     const bool live = g < KG && g > 0;
     int g1 = 0, g2 = 0;
@@ -307,9 +358,11 @@ __global__ __launch_bounds__(256) void k_self(int N, int M, int K, int GM, int K
 hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd, hipStream_t st, DevClock* bump)
 {
     if (stage2_uses_mfma(T.M, dd, !B.interact)) return bump ? hipErrorInvalidValue : launch_self_pad(T, B, cur, st);
-    const int threads = 256;
+    const int threads = kSelfVThreads;
     dim3 grid(((dd ? 8 : 4) * T.KG + threads - 1) / threads, B.N);
     const int nt0 = (T.T0N + 1) * (T.T0N + 2) / 2;
+    // the fill covers at most kSelfFillA and kSelfFillT rounds of the workgroup
+    if (T.K > kSelfFillA * threads || nt0 > kSelfFillT * threads) return hipErrorInvalidValue;
     size_t shmem = sizeof(double) * ((size_t)T.K + (dd ? 2 : 1) * (size_t)nt0);
     if (dd)
         launch_kernel(k_self<true>, grid, dim3(threads), shmem, st, B.N, T.M, T.K, T.GM, T.KG, T.T0N,
@@ -930,7 +983,14 @@ template <bool APPLY>
 __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBufs B, int cur, ApplyArgs P)
 {
     const int M = T.M, GM = T.GM;
-    const int r = blockIdx.x, par = blockIdx.y & 1, j = blockIdx.y >> 1;
+    // The hardware deals consecutive workgroup ids to the 8 XCDs in turn.  The
+    // rows of one (vortex, parity) all read that vortex's partial sums and state
+    // of that parity, so the ids are renumbered to give each XCD a contiguous
+    // run of rows: its L2 then fetches those operands once (the grid has
+    // RP * 2N workgroups, RP a multiple of 16, so the runs are equal).
+    const int nblk = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const int vid = (lin & 7) * (nblk >> 3) + (lin >> 3);
+    const int r = vid % gridDim.x, par = (vid / gridDim.x) & 1, j = (vid / gridDim.x) >> 1;
     const S2Shape sh(M, par);
     const T0Shape tz(M);
     const int LP = sh.LP, TP = tz.TP, LDA = LP + 2, LDB = TP + 2, LDQ = TP + 1;
@@ -1514,13 +1574,9 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
     // few vortices: wide workgroups for latency; many: one to four wavefronts each
     int threads = B.N <= 32 ? 1024 : (Sh::NY >= 1024 ? 256 : (Sh::NY >= 256 ? 128 : 64));
     if (shmem > 64 * 1024) {
-        hipError_t ea = hipFuncSetAttribute((const void*)k_stage2_small<M>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (ea != hipSuccess) {
-            (void)hipGetLastError();
-            report_hip_error(ea, "hipFuncSetAttribute(k_stage2_small dynamic LDS)");
-            return ea;
-        }
+        const hipError_t ea =
+            lds_limit_once((const void*)k_stage2_small<M>, shmem, "hipFuncSetAttribute(k_stage2_small dynamic LDS)");
+        if (ea != hipSuccess) return ea;
     }
     launch_kernel(k_stage2_small<M>, dim3(B.N), dim3(threads), shmem, st, T, B, A);
     return hipGetLastError();
@@ -1534,13 +1590,9 @@ static hipError_t launch_solo_M(const DevTables& T, int nb, const double* lam0sq
     if (T.T0N != Sh::T0N) return hipErrorInvalidValue;
     const size_t shmem = sizeof(double) * (size_t)Sh::TOTAL;
     if (shmem > 64 * 1024) {
-        hipError_t ea = hipFuncSetAttribute((const void*)k_solo_rk4<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)shmem);
-        if (ea != hipSuccess) {
-            (void)hipGetLastError();
-            report_hip_error(ea, "hipFuncSetAttribute(k_solo_rk4 dynamic LDS)");
-            return ea;
-        }
+        const hipError_t ea =
+            lds_limit_once((const void*)k_solo_rk4<M>, shmem, "hipFuncSetAttribute(k_solo_rk4 dynamic LDS)");
+        if (ea != hipSuccess) return ea;
     }
     const int threads = Sh::K > 256 ? 1024 : kSoloThreads;
     launch_kernel(k_solo_rk4<M>, dim3(nb), dim3(threads), shmem, st, T, lam0sq, nuv, t0, dt, nsteps, mom, flag);
@@ -1592,15 +1644,12 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     if (!use_dd) {
         if (!stage2_uses_mfma(T.M, use_dd, !B.interact) || B.interact) return hipErrorInvalidValue;
         const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
-        // the attribute is set to the largest order's size once, so that no
-        // launch (possibly captured into a graph) makes the call
-        static const hipError_t ea = hipFuncSetAttribute(
-            (const void*)k_stage2_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)(sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder)));
-        if (ea != hipSuccess || shmem > sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder)) {
-            report_hip_error(ea, "hipFuncSetAttribute(k_stage2_mfma dynamic LDS)");
-            return ea != hipSuccess ? ea : hipErrorInvalidValue;
-        }
+        // the limit is the largest order's size for every order
+        const size_t most = sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder);
+        if (shmem > most) return hipErrorInvalidValue;
+        const hipError_t ea =
+            lds_limit_once((const void*)k_stage2_mfma, most, "hipFuncSetAttribute(k_stage2_mfma dynamic LDS)");
+        if (ea != hipSuccess) return ea;
         launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();
     }
@@ -1610,19 +1659,13 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     // more: the smaller layout, two workgroups per CU
     const bool ctab = 4 * M1 * B.N <= kDDOneRound;
     const size_t shmem = sizeof(double) * (size_t)DDShape(T.M, 0, ctab).total;
-    // each variant's attribute is set once, to the largest order's size (no
-    // launch, possibly captured into a graph, makes the call)
-    static const hipError_t ea_t = hipFuncSetAttribute(
-        (const void*)k_stage2_dd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(sizeof(double) * (size_t)DDShape(MMVM_MAX_ORDER, 0, true).total));
-    static const hipError_t ea_f = hipFuncSetAttribute(
-        (const void*)k_stage2_dd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(sizeof(double) * (size_t)DDShape(MMVM_MAX_ORDER, 0, false).total));
-    const hipError_t ea = ctab ? ea_t : ea_f;
-    if (ea != hipSuccess) {
-        report_hip_error(ea, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
-        return ea;
-    }
+    // each variant's limit is the largest order's size for every order
+    const size_t most = sizeof(double) * (size_t)DDShape(MMVM_MAX_ORDER, 0, ctab).total;
+    if (shmem > most) return hipErrorInvalidValue;
+    const hipError_t ea =
+        ctab ? lds_limit_once((const void*)k_stage2_dd<true>, most, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)")
+             : lds_limit_once((const void*)k_stage2_dd<false>, most, "hipFuncSetAttribute(k_stage2_dd dynamic LDS)");
+    if (ea != hipSuccess) return ea;
     if (ctab) launch_kernel(k_stage2_dd<true>, grid, dim3(kDDThreads), shmem, st, T, B, A);
     else launch_kernel(k_stage2_dd<false>, grid, dim3(kDDThreads), shmem, st, T, B, A);
     return hipGetLastError();
