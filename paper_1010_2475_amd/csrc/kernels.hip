@@ -771,32 +771,53 @@ struct View {
 // D[row0 + l/16 + 4q][col0 + l%16] in component q.  All operands are loaded
 // first, then two accumulator chains alternate k-steps.
 template <int KS>
-__device__ __forceinline__ dbl4 mfma_tile(int lane, int row0, int col0, int s0, int s1, const View& A, const View& B)
+struct TileOps {
+    double a[KS], b[KS];
+    int s0, s1;
+};
+
+template <int KS>
+__device__ __forceinline__ void tile_load(TileOps<KS>& o, int lane, int row0, int col0, int s0, int s1, const View& A,
+                                          const View& B)
 {
     const int lk = lane >> 4;
     const double* pa = A.p + (row0 + (lane & 15)) * A.rs + (4 * s0 + lk) * A.cs;
     const double* pb = B.p + (4 * s0 + lk) * B.rs + (col0 + (lane & 15)) * B.cs;
     const int sa = 4 * A.cs, sb = 4 * B.rs;
-    double a[KS], b[KS];
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
         if (s0 + q < s1) {
-            a[q] = pa[q * sa];
-            b[q] = pb[q * sb];
+            o.a[q] = pa[q * sa];
+            o.b[q] = pb[q * sb];
         } else {
-            a[q] = 0.0;
-            b[q] = 0.0;
+            o.a[q] = 0.0;
+            o.b[q] = 0.0;
         }
     }
+    o.s0 = s0;
+    o.s1 = s1;
+}
+
+template <int KS>
+__device__ __forceinline__ dbl4 tile_mfma(const TileOps<KS>& o)
+{
     dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < KS; ++q) {
-        if (s0 + q < s1) {
-            if (q & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc1, 0, 0, 0);
-            else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc0, 0, 0, 0);
+        if (o.s0 + q < o.s1) {
+            if (q & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[q], o.b[q], acc1, 0, 0, 0);
+            else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[q], o.b[q], acc0, 0, 0, 0);
         }
     }
     return acc0 + acc1;
+}
+
+template <int KS>
+__device__ __forceinline__ dbl4 mfma_tile(int lane, int row0, int col0, int s0, int s1, const View& A, const View& B)
+{
+    TileOps<KS> o;
+    tile_load(o, lane, row0, col0, s0, s1, A, B);
+    return tile_mfma(o);
 }
 
 // largest order of the matrix-core stage 2 and the per-wavefront bounds it implies
@@ -804,6 +825,11 @@ constexpr int kS2TilesPerWave = 2;                         // output tiles of (B
 constexpr int kS2KA = ((2 * kS2MaxOrder) >> 2) + 1;        // k-steps of (A)
 constexpr int kS2KB = kS2MaxOrder / 4 + 1;                 // k-steps of (B) and (C)
 static_assert(((kS2MaxOrder + 16) / 16) * ((kS2MaxOrder + 16) / 16) <= kS2TilesPerWave * kS2Waves, "tiles");
+// k-steps of an (A) tile in the third row of tiles (g1 >= 64, so g2 <= 2 kS2MaxOrder - 64)
+constexpr int kS2KA3 = ((2 * kS2MaxOrder - 64) >> 2) + 1;
+static_assert(kS2Waves == 8 && 16 * ((kS2MaxOrder + 16) / 16) <= 48, "at most nine (A) tiles, three by three");
+// output tiles of (C) per wavefront: d over 2 (M - k2) + 1 <= 2 M + 1 rows, i over M + 1 columns
+constexpr int kS2TilesC = (((2 * kS2MaxOrder + 1 + 15) / 16) * ((kS2MaxOrder + 1 + 15) / 16) + kS2Waves - 1) / kS2Waves;
 static_assert(kS2MaxOrder < 64, "one lane per k1 in the last step");
 static_assert(MMVM_MAX_ORDER <= kS2MaxOrder, "order");
 
@@ -884,19 +910,46 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     // (A)
     {
         const View va = {gS, sh.LDS, 1}, vb = {gW, LP, 1};
-        for (int t = wave; t < tr * tc; t += kS2Waves) {
-            const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
-            // W[.][l2] is nonzero for g2 in [lo(l2), k2 + l2 + off2], lo = 1 + |l2 - k2| (pass 0),
-            // |l2 - k2 + 1| (pass 1); row r0 ends at g2 = GM - par - 2 r0
+        // the k-steps of tile t: W[.][l2] is nonzero for g2 in [lo(l2), k2 + l2 + off2],
+        // lo = 1 + |l2 - k2| (pass 0), |l2 - k2 + 1| (pass 1); row r0 ends at g2 = GM - par - 2 r0
+        auto krange = [&](int t, int& r0, int& c0, int& s0, int& s1) {
+            r0 = (t / tc) * 16;
+            c0 = (t % tc) * 16;
             const int lhi = c0 + 15 < M ? c0 + 15 : M;
             const int dist = imaxk < c0 ? c0 - imaxk : (imaxk > lhi ? imaxk - lhi : 0);
             const int glo = (pass == 0 ? 1 : 0) + dist;
             int ghi = k2 + off2 + lhi;
             if (ghi > GM - par - 2 * r0) ghi = GM - par - 2 * r0;
-            const int s0 = glo >> 2, s1 = (c0 <= M && glo <= ghi) ? (ghi >> 2) + 1 : s0;
-            const dbl4 d = mfma_tile<kS2KA>(lane, r0, c0, s0, s1, va, vb);
+            s0 = glo >> 2;
+            s1 = (c0 <= M && glo <= ghi) ? (ghi >> 2) + 1 : s0;
+        };
+        auto put = [&](int r0, int c0, const dbl4& d) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) sY[(r0 + (lane >> 4) + 4 * q) * sh.LDY + c0 + (lane & 15)] = d[q];
+        };
+        if (tr * tc <= kS2Waves || wave < kS2Waves - 2) {
+            // a tile per wavefront (the first six of nine)
+            if (wave < tr * tc) {
+                int r0, c0, s0, s1;
+                krange(wave, r0, c0, s0, s1);
+                put(r0, c0, mfma_tile<kS2KA>(lane, r0, c0, s0, s1, va, vb));
+            }
+        } else {
+            // nine tiles (orders 32 and up): the last row of tiles (rows g1 >= 64,
+            // where S is nonzero for g2 <= GM - 64 only) has at most kS2KA3
+            // k-steps a tile.  Wavefront 6 takes tiles 6 and 8, with the operands
+            // of both loaded first; wavefront 7 takes tile 7.
+            TileOps<kS2KA3> o[2];
+            int r0[2], c0[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                int s0, s1;
+                krange(wave + 2 * u, r0[u], c0[u], s0, s1);
+                if (u == 1 && wave != kS2Waves - 2) s1 = s0;
+                tile_load(o[u], lane, r0[u], c0[u], s0, s1, va, vb);
+            }
+            put(r0[0], c0[0], tile_mfma(o[0]));
+            if (wave == kS2Waves - 2) put(r0[1], c0[1], tile_mfma(o[1]));
         }
     }
     __syncthreads();
@@ -929,21 +982,39 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     __syncthreads();
     // (C) U = T(sheared) x C; U overwrites Y, whose last reads preceded the barrier
     {
-        const int td = (nd + 15) >> 4, ti = (ni + 15) >> 4;
+        // a wavefront takes tiles wave, wave + 8, ...; the operands of its next
+        // tile load while the current one multiplies (two register buffers)
+        const int td = (nd + 15) >> 4, ti = (ni + 15) >> 4, ntc = td * ti;
         const View va = {sT + (dlo + kS2TPad) * sh.LDT, sh.LDT, sh.LDT + 1}, vb = {T.cpad, LP, 1};
-        for (int t = wave; t < td * ti; t += kS2Waves) {
-            const int r0 = (t / ti) * 16, c0 = (t % ti) * 16;
-            // l1 >= i >= c0 and 0 <= d + l1 <= GM
-            int llo = -(dlo + r0 + 15);
-            if (llo < c0) llo = c0;
-            int lhi = GM - (dlo + r0);
-            if (lhi > M) lhi = M;
-            const int s0 = llo >> 2, s1 = llo <= lhi ? (lhi >> 2) + 1 : s0;
-            const dbl4 d = mfma_tile<kS2KB>(lane, r0, c0, s0, s1, va, vb);
+        TileOps<kS2KB> op[2];
+        int r0[kS2TilesC], c0[kS2TilesC];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int di = r0 + (lane >> 4) + 4 * q, i = c0 + (lane & 15);
-                if (di < nd && i < ni) sU[di * ni + i] = d[q];
+        for (int u = 0; u < kS2TilesC; ++u) {
+            const int t = wave + u * kS2Waves;
+            r0[u] = (t / ti) * 16;
+            c0[u] = (t % ti) * 16;
+        }
+        // l1 >= i >= c0 and 0 <= d + l1 <= GM; no k-steps past the tiles of this wavefront
+        auto load = [&](int u) {
+            int llo = -(dlo + r0[u] + 15);
+            if (llo < c0[u]) llo = c0[u];
+            int lhi = GM - (dlo + r0[u]);
+            if (lhi > M) lhi = M;
+            const int s0 = llo >> 2;
+            const int s1 = (wave + u * kS2Waves < ntc && llo <= lhi) ? (lhi >> 2) + 1 : s0;
+            tile_load(op[u & 1], lane, r0[u], c0[u], s0, s1, va, vb);
+        };
+        load(0);
+#pragma unroll
+        for (int u = 0; u < kS2TilesC; ++u) {
+            if (u + 1 < kS2TilesC) load(u + 1);
+            const dbl4 d = tile_mfma(op[u & 1]);
+            if (wave + u * kS2Waves < ntc) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int di = r0[u] + (lane >> 4) + 4 * q, i = c0[u] + (lane & 15);
+                    if (di < nd && i < ni) sU[di * ni + i] = d[q];
+                }
             }
         }
     }
