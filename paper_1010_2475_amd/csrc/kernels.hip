@@ -821,13 +821,13 @@ __device__ __forceinline__ dbl4 mfma_tile(int lane, int row0, int col0, int s0, 
 }
 
 // largest order of the matrix-core stage 2 and the per-wavefront bounds it implies
-constexpr int kS2TilesPerWave = 2;                         // output tiles of (B) held per wavefront
 constexpr int kS2KA = ((2 * kS2MaxOrder) >> 2) + 1;        // k-steps of (A)
 constexpr int kS2KB = kS2MaxOrder / 4 + 1;                 // k-steps of (B) and (C)
-static_assert(((kS2MaxOrder + 16) / 16) * ((kS2MaxOrder + 16) / 16) <= kS2TilesPerWave * kS2Waves, "tiles");
 // k-steps of an (A) tile in the third row of tiles (g1 >= 64, so g2 <= 2 kS2MaxOrder - 64)
 constexpr int kS2KA3 = ((2 * kS2MaxOrder - 64) >> 2) + 1;
 static_assert(kS2Waves == 8 && 16 * ((kS2MaxOrder + 16) / 16) <= 48, "at most nine (A) tiles, three by three");
+// k-steps of a (B) tile in the third column of tiles (l1 >= 32, so l2 <= kS2MaxOrder - 32)
+constexpr int kS2KB3 = (kS2MaxOrder - 32) / 4 + 1;
 // output tiles of (C) per wavefront: d over 2 (M - k2) + 1 <= 2 M + 1 rows, i over M + 1 columns
 constexpr int kS2TilesC = (((2 * kS2MaxOrder + 1 + 15) / 16) * ((kS2MaxOrder + 1 + 15) / 16) + kS2Waves - 1) / kS2Waves;
 static_assert(kS2MaxOrder < 64, "one lane per k1 in the last step");
@@ -953,30 +953,38 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
         }
     }
     __syncthreads();
-    // (B): the results stay in registers until every wavefront has read Y
+    // (B) T[r][l1] = sum_{l2} Y[r][l2] (-1)^{|l|} alpha[l1, l2]
     {
         const View va = {sY, sh.LDY, 1}, vb = {gA, LP, 1};
-        dbl4 dt[kS2TilesPerWave];
+        auto put = [&](int t, const dbl4& d) {
+            const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
 #pragma unroll
-        for (int q = 0; q < kS2TilesPerWave; ++q) {
-            const int t = wave + q * kS2Waves;
-            if (t < tr * tc) {
-                const int c0 = (t % tc) * 16;
-                const int s1 = c0 <= M ? (M - c0) / 4 + 1 : 0;
-                dt[q] = mfma_tile<kS2KB>(lane, (t / tc) * 16, c0, 0, s1, va, vb);
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + (lane >> 4) + 4 * u, l1 = c0 + (lane & 15);
+                if (r < nrp) sT[(par + 2 * r + kS2TPad) * sh.LDT + l1] = d[u];
             }
-        }
-#pragma unroll
-        for (int q = 0; q < kS2TilesPerWave; ++q) {
-            const int t = wave + q * kS2Waves;
-            if (t < tr * tc) {
-                const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int r = r0 + (lane >> 4) + 4 * u, l1 = c0 + (lane & 15);
-                    if (r < nrp) sT[(par + 2 * r + kS2TPad) * sh.LDT + l1] = dt[q][u];
-                }
-            }
+        };
+        // l2 <= M - l1 < M - c0 + 1
+        auto steps = [&](int t) {
+            const int c0 = (t % tc) * 16;
+            return c0 <= M ? (M - c0) / 4 + 1 : 0;
+        };
+        if (tr * tc <= kS2Waves) {
+            if (wave < tr * tc) put(wave, mfma_tile<kS2KB>(lane, (wave / tc) * 16, (wave % tc) * 16, 0, steps(wave), va, vb));
+        } else if (wave < kS2Waves - 2) {
+            // nine tiles: wavefronts 0..5 take the first two columns of tiles
+            const int t = (wave >> 1) * 3 + (wave & 1);
+            put(t, mfma_tile<kS2KB>(lane, (t / tc) * 16, (t % tc) * 16, 0, steps(t), va, vb));
+        } else {
+            // the third column (l1 >= 32) has at most kS2KB3 k-steps a tile:
+            // wavefront 6 takes tiles 2 and 8 (the operands of both loaded
+            // first), wavefront 7 takes tile 5
+            const int ta = wave == kS2Waves - 2 ? 2 : 5;
+            TileOps<kS2KB3> o[2];
+            tile_load(o[0], lane, (ta / tc) * 16, (ta % tc) * 16, 0, steps(ta), va, vb);
+            tile_load(o[1], lane, 32, 32, 0, wave == kS2Waves - 2 ? steps(8) : 0, va, vb);
+            put(ta, tile_mfma(o[0]));
+            if (wave == kS2Waves - 2) put(8, tile_mfma(o[1]));
         }
     }
     __syncthreads();
