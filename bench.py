@@ -65,9 +65,9 @@ def self_flops(M):
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
 # and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3272.4, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.6,
-                  "write_scale": 262144.0 / 262146.3,
-                  "sources_sha256": {"kernels.hip": "83c251f5e838b105b96f0c44b453920fcf060f7bb83a48a8f93392d0d6bbf39d",
+TRAFFIC_STAGE2 = {"fetch_kib": 3315.3, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.5,
+                  "write_scale": 262144.0 / 262148.5,
+                  "sources_sha256": {"kernels.hip": "b0154482507c45143afdf6677880d9cc822214326dd19ac6e40856d89837c79c",
                                      "kernels.hpp": "3375d55249804302b7f19d77820bd8e2815f2cb4916c061604557fc53805903d"}}
 
 
