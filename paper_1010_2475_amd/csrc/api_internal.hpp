@@ -26,7 +26,7 @@ struct Workspace {
     std::vector<double> par_cache;
     hipEvent_t par_event = nullptr;    // the upload from par_cache has completed
     int latched = 0;
-    // captured stepping graph (two RK4 steps of the matrix-core path, or one of
+    // captured stepping graph (eight RK4 steps of the matrix-core path, or one of
     // the double-double path), reused while its key (kind, order, batch, dt,
     // tables, the caller's state for the double-double path) holds; see stepper.cpp
     DevClock* clock = nullptr;

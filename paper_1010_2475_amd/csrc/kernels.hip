@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     const double* gD = pass == 0 ? T.fd1 : T.fd0;
     // graph replay: the last stage of the captured steps advances the clock
     // (every reader of it, a self kernel, has finished; the next one starts after)
-    if (S.clock_bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) S.clock_bump->n += 2;
+    if (S.clock_bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) S.clock_bump->n += S.clock_steps;
 
     // T is zero except the rows of this parity written after (B)
     {

@@ -88,7 +88,8 @@ struct StageArgs {
     double* mom;       // user moments    [N][K]
     double* dx;        // RHS output      [N][2]
     double* dmom;      // RHS output      [N][K]
-    DevClock* clock_bump;  // graph replay: the matrix-core stage 2 advances clock.n by 2
+    DevClock* clock_bump;  // graph replay: the matrix-core stage 2 advances clock.n by clock_steps
+    int clock_steps;
     // graph replay of the double-double path: when clock is set the emit
     // kernel takes t_next = t0 + (clock.n + n_rel + c_next) dt (the step's
     // first self kernel advances clock.n, see launch_self)

@@ -14,11 +14,14 @@ namespace mmvm {
 //
 // Steps 1 .. nsteps-1 repeat with period two (the state buffer alternates by
 // step; the stage buffers return to buffer 0 after four stages), so they run
-// as replays of one captured two-step graph when there are enough of them.
-// The replays take their stage times from a device clock (t0, n) that the
-// graph's last node advances by two steps; the graph is kept in the workspace
-// and reused by later calls with the same order, batch and dt.
+// as replays of one captured graph of kGraphSteps steps (an even number) when
+// there are enough of them.  The replays take their stage times from a device
+// clock (t0, n) that the graph's last node advances by kGraphSteps; the graph
+// is kept in the workspace and reused by later calls with the same order,
+// batch and dt.  Several steps per graph leave fewer gaps between replays.
 static const double kStageC[5] = {0.0, 0.5, 0.5, 1.0, 1.0};
+constexpr int kGraphSteps = 8;
+static_assert(kGraphSteps % 2 == 0, "the state buffers alternate by step");
 constexpr int64_t kGraphMinSteps = 8;
 
 // MMVM_GRAPHS=0 in the environment keeps every step on direct launches
@@ -60,6 +63,7 @@ static hipError_t launch_step(const DevTables& T, Workspace& W, StageArgs A, dou
         A.t_stage = ts;
         A.t_next = t0 + ((double)n + kStageC[s + 1]) * A.dt;
         A.clock_bump = (bump && s == 3) ? clock : nullptr;
+        A.clock_steps = kGraphSteps;
         tk = timing_begin(st);
         e = launch_stage2(T, W.bufs, A, false, st);
         timing_end(tk, "stage2", st);
@@ -124,8 +128,9 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
     if (kind == kGraphDD) {
         e = launch_dd_step(T, W, A, cs);
     } else {
-        e = launch_step(T, W, A, 0.0, 0, W.clock, false, cs);
-        if (e == hipSuccess) e = launch_step(T, W, A, 0.0, 1, W.clock, true, cs);
+        e = hipSuccess;
+        for (int q = 0; q < kGraphSteps && e == hipSuccess; ++q)
+            e = launch_step(T, W, A, 0.0, q, W.clock, q == kGraphSteps - 1, cs);
     }
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
@@ -188,15 +193,15 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
         }
     }
     int64_t n = 1;
-    if (e == hipSuccess && nsteps - 1 >= kGraphMinSteps && graphs_enabled() && !timing_on() && W.clock) {
+    if (e == hipSuccess && nsteps - 1 >= kGraphSteps && graphs_enabled() && !timing_on() && W.clock) {
         hipGraphExec_t g = stepping_graph(T, W, A, kGraphMFMA, st);
         if (g) {
-            const int64_t reps = (nsteps - 1) / 2;
+            const int64_t reps = (nsteps - 1) / kGraphSteps;
             e = launch_set_clock(W.clock, t0, 1, st);
             for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
             if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
             if (e == hipSuccess) count_graph_replays(reps);
-            n += 2 * reps;
+            n += kGraphSteps * reps;
         }
     }
     for (; n < nsteps && e == hipSuccess; ++n) e = launch_step(T, W, A, t0, n, nullptr, false, st);
