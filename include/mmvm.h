@@ -170,7 +170,7 @@ mmvm_status mmvm_server_destroy(mmvm_server* srv);
  * The name "graph" returns, timing on or off, the number of replays of
  * captured stepping graphs since the process started (total_ms = 0): calls
  * of at least 9 steps on the large-order paths replay a captured graph (eight
- * steps on the matrix-core path, one step on the double-double path) unless
+ * steps on the matrix-core path, four on the double-double path) unless
  * timing is on or the environment variable MMVM_GRAPHS is 0. */
 mmvm_status mmvm_timing_enable(int32_t on);
 mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launches);

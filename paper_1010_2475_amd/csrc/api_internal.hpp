@@ -26,8 +26,8 @@ struct Workspace {
     std::vector<double> par_cache;
     hipEvent_t par_event = nullptr;    // the upload from par_cache has completed
     int latched = 0;
-    // captured stepping graph (eight RK4 steps of the matrix-core path, or one of
-    // the double-double path), reused while its key (kind, order, batch, dt,
+    // captured stepping graph (eight RK4 steps of the matrix-core path, or four
+    // of the double-double path), reused while its key (kind, order, batch, dt,
     // tables, the caller's state for the double-double path) holds; see stepper.cpp
     DevClock* clock = nullptr;
     hipStream_t cap_stream = nullptr;  // where the graph is captured

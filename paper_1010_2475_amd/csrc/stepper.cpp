@@ -97,6 +97,7 @@ static hipError_t launch_dd_step(const DevTables& T, Workspace& W, StageArgs A, 
 }
 
 enum { kGraphMFMA = 0, kGraphDD = 1 };
+constexpr int kDDGraphSteps = 4;  // steps per graph of the double-double path
 
 // The workspace's stepping graph of this kind for this (order, batch, dt, and
 // for the double-double path the caller's state), captured on first use; null
@@ -126,7 +127,8 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
     }
     hipError_t e;
     if (kind == kGraphDD) {
-        e = launch_dd_step(T, W, A, cs);
+        e = hipSuccess;
+        for (int q = 0; q < kDDGraphSteps && e == hipSuccess; ++q) e = launch_dd_step(T, W, A, cs);
     } else {
         e = hipSuccess;
         for (int q = 0; q < kGraphSteps && e == hipSuccess; ++q)
@@ -250,23 +252,26 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, in
     mmvm_status r = run_prep(T, W, cur, x, mom, t0, prec, st);
     if (r != MMVM_OK) return r;
     if (stage2_fuses_emit(T.M, use_dd(T.M, prec), !W.bufs.interact)) return run_steps_fused(T, W, A, t0, nsteps, st);
-    // the double-double path (single vortices): step 0 direct, the rest as
-    // replays of a one-step graph on a clock that starts at step 0
+    // the double-double path (single vortices): step 0 direct, then replays
+    // of a kDDGraphSteps-step graph on a clock that starts at step 0, then
+    // the remaining steps direct
     const bool dd_graph = use_dd(T.M, prec) && !W.bufs.interact && nsteps - 1 >= kGraphMinSteps &&
                           graphs_enabled() && !timing_on() && W.clock;
     for (int64_t n = 0; n < nsteps; ++n) {
         if (n == 1 && dd_graph) {
             hipGraphExec_t g = stepping_graph(T, W, A, kGraphDD, st);
             if (g) {
+                const int64_t reps = (nsteps - 1) / kDDGraphSteps;
                 hipError_t e = launch_set_clock(W.clock, t0, 0, st);
-                for (int64_t r = 1; r < nsteps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
+                for (int64_t q = 0; q < reps && e == hipSuccess; ++q) e = hipGraphLaunch(g, st);
                 if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
                 if (e != hipSuccess) {
                     report_hip_error(e, "stepping graph replay");
                     return MMVM_EDEVICE;
                 }
-                count_graph_replays(nsteps - 1);
-                return MMVM_OK;
+                count_graph_replays(reps);
+                n += kDDGraphSteps * reps;  // the rest is launched directly
+                if (n >= nsteps) return MMVM_OK;
             }
         }
         for (int s = 0; s < 4; ++s) {

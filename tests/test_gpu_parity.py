@@ -320,7 +320,7 @@ def _step_env(env, w, t0, nsteps, prec, graphs, X=None, Mo=None):
                                            (40, 0, 12)])
 def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
     """Large-order stepping replays a captured graph (eight steps on the matrix
-    cores; one step of the double-double path, FP64 above order 24) whose
+    cores; four steps of the double-double path, FP64 above order 24) whose
     stage times come from a device clock; it must give the bits of direct
     launches, also when a second call recaptures it for other state buffers,
     with other work between, and when a third call reuses it."""
@@ -329,7 +329,7 @@ def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
     w = wl.single_random(M=M, Re=700.0, seed=M)
     w.dt = 2e-3
     dd = prec == 0 and M > 24
-    reps = (nsteps - 1) if dd else (nsteps - 1) // 8
+    reps = (nsteps - 1) // 4 if dd else (nsteps - 1) // 8
     r0 = mm.timing_get("graph")[1]
     _, m_d = _step_env(env, w, 0.05, nsteps, prec, False)
     assert mm.timing_get("graph")[1] == r0
