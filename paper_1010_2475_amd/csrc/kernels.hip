@@ -1062,14 +1062,33 @@ template <bool APPLY>
 __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBufs B, int cur, ApplyArgs P)
 {
     const int M = T.M, GM = T.GM;
-    // The hardware deals consecutive workgroup ids to the 8 XCDs in turn.  The
-    // rows of one (vortex, parity) all read that vortex's partial sums and state
-    // of that parity, so the ids are renumbered to give each XCD a contiguous
-    // run of rows: its L2 then fetches those operands once (the grid has
-    // RP * 2N workgroups, RP a multiple of 16, so the runs are equal).
-    const int nblk = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
-    const int vid = (lin & 7) * (nblk >> 3) + (lin >> 3);
-    const int r = vid % gridDim.x, par = (vid / gridDim.x) & 1, j = (vid / gridDim.x) >> 1;
+    // Workgroup ids are renumbered.  The rows with work (r < nrp of each
+    // parity) come first, so that they take a CU each, and the rows beyond the
+    // triangle, which only write zeros, are dispatched last.  The hardware
+    // deals consecutive ids to the 8 XCDs in turn, and the rows of one
+    // (vortex, parity) all read that vortex's partial sums and state of that
+    // parity, so each XCD takes a contiguous run of rows (its L2 then fetches
+    // those operands once).
+    int r, par, j;
+    {
+        const int n0 = S2Shape(M, 0).nrp, n1 = S2Shape(M, 1).nrp, RPg = gridDim.x;
+        const int per = n0 + n1, nwork = (gridDim.y >> 1) * per;
+        const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+        if (lin < nwork) {
+            const int xcd = lin & 7, q8 = nwork >> 3, r8 = nwork & 7;
+            const int vid = xcd * q8 + (xcd < r8 ? xcd : r8) + (lin >> 3);
+            j = vid / per;
+            const int w = vid - j * per;
+            par = w < n0 ? 0 : 1;
+            r = par == 0 ? w : w - n0;
+        } else {
+            const int z = lin - nwork, perz = (RPg - n0) + (RPg - n1);
+            j = z / perz;
+            const int w = z - j * perz;
+            par = w < RPg - n0 ? 0 : 1;
+            r = par == 0 ? n0 + w : n1 + (w - (RPg - n0));
+        }
+    }
     const S2Shape sh(M, par);
     const T0Shape tz(M);
     const int LP = sh.LP, TP = tz.TP, LDA = LP + 2, LDB = TP + 2, LDQ = TP + 1;
