@@ -273,7 +273,7 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     size_t need = 0;
     auto add = [&](size_t n) {
         size_t o = need;
-        need += (n + 63) & ~(size_t)63;
+        need += (n + 255) & ~(size_t)255;  // 256-byte aligned regions: whole cache lines
         return o;
     };
     L.flag = add(sizeof(int) * 16);  // first: fixed offset across layouts

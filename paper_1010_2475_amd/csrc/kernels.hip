@@ -857,8 +857,9 @@ bool stage2_uses_mfma(int M, bool dd, bool solo)
 //        U[d][i]   = sum_{l1} T[d + l1][l1] C(l1, i),
 //        G[k1]     = -+ sum_i F'[k1][i][i] U[k1 - 2i -+ 1][i].
 // Rows r index g1 = par + 2r (the rows of this workgroup's parity).  The self
-// kernel writes S in exactly this padded row layout and W and C come padded
-// from the tables, so staging them is a plain copy.  Every output tile runs
+// kernel writes S zero-padded and by columns (the 16 rows of an operand
+// fragment are one cache line), and W and C come padded from the tables, so
+// the operands are read in place.  Every output tile runs
 // only over the k-steps where its band of W, the triangle of alpha or the
 // triangle of C is nonzero.  T is stored by (g1, l1) with zero rows for the
 // other parity and kS2TPad zero rows on either side, so that the sheared
@@ -891,7 +892,7 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     double* sY = smem + sh.y;             // Y [RP][LDY]                   (A -> B)
     double* sU = smem + sh.y;             // U [nd][ni], over Y            (C -> last step)
     double* sP = smem + sh.ps;            // partial sums of the last step [8][64]
-    const double* gS = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS;
+    const double* gS = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.KA;  // column-major: 16 rows = one line
     const double* gW = T.wpad + ((long)k2 * 2 + pass) * KA * LP;
     const double* gA = B.alphaS[S.cur] + (long)j * LP * LP;
     const double* gD = pass == 0 ? T.fd1 : T.fd0;
@@ -909,7 +910,7 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
     const int tr = sh.RP >> 4, tc = LP >> 4;
     // (A)
     {
-        const View va = {gS, sh.LDS, 1}, vb = {gW, LP, 1};
+        const View va = {gS, 1, sh.RP}, vb = {gW, LP, 1};
         // the k-steps of tile t: W[.][l2] is nonzero for g2 in [lo(l2), k2 + l2 + off2],
         // lo = 1 + |l2 - k2| (pass 0), |l2 - k2 + 1| (pass 1); row r0 ends at g2 = GM - par - 2 r0
         auto krange = [&](int t, int& r0, int& c0, int& s0, int& s1) {
@@ -1049,8 +1050,8 @@ __global__ __launch_bounds__(kS2Threads) void k_stage2_mfma(DevTables T, StageBu
 }
 
 // ---------------------------------------------------------------------------
-// Self velocity-derivative table of the matrix-core path, written in the
-// padded row layout of each parity: s_pad[j][par][r][c] = S_self[g1 = par + 2r][g2 = c]
+// Self velocity-derivative table of the matrix-core path, written zero-padded
+// by columns for each parity: s_pad[j][par][c][r] = S_self[g1 = par + 2r][g2 = c]
 // (zero beyond the triangle and at g = 0).  Workgroup = (row r, parity, vortex).
 // With Psi0(2a, 2b) = t0[a][b] and m1 of the parity of g1 (m1 = p1 + 2 m1'):
 //   Q[m2][b]  = sum_{m1'} alpha[p1 + 2 m1'][m2] t0[m1' + ceil(g1 / 2)][b]   (matrix cores)
@@ -1098,9 +1099,9 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     const int len = r < sh.nrp ? GM - g1 + 1 : 0;
     const int p1 = g1 & 1, sh1 = (g1 + p1) >> 1;
     const int ks = (((M - p1) >> 1) + 4) >> 2;  // m1' < 4 ks covers m1 <= M
-    double* out = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.LDS + (long)r * sh.LDS;
+    double* out = B.s_pad + ((long)j * 2 + par) * sh.RP * sh.KA + r;  // column g2 at out[g2 * RP]
     if (len == 0 && r != 0) {  // rows beyond the triangle
-        for (int c = tid; c < sh.LDS; c += kSelfThreads) out[c] = 0.0;
+        for (int c = tid; c < sh.KA; c += kSelfThreads) out[(long)c * sh.RP] = 0.0;
         return;
     }
     extern __shared__ double smem[];
@@ -1223,14 +1224,14 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
     }
     __syncthreads();
     // S[g1][g2] = sum over m2 of the parity of g2; four lanes per entry
-    for (int t = tid; t < 4 * sh.LDS; t += kSelfThreads) {
+    for (int t = tid; t < 4 * sh.KA; t += kSelfThreads) {
         const int g2 = t >> 2, q = t & 3;
         double acc = 0.0;
         if (g2 < len)
             for (int m2 = (g2 & 1) + 2 * q; m2 <= M; m2 += 8) acc += sQ[m2 * LDQ + ((m2 + g2) >> 1)];
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
-        if (q == 0) out[g2] = (g2 < len && g1 + g2 > 0) ? acc : 0.0;
+        if (q == 0) out[(long)g2 * sh.RP] = (g2 < len && g1 + g2 > 0) ? acc : 0.0;
     }
 }
 

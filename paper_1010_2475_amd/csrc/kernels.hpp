@@ -55,7 +55,7 @@ struct StageBufs {
     double* s_self;        // [N][KG] self velocity-derivative table (lambda units)
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
-    double* s_pad;         // [N][2][RP][LDS] self table by rows of each parity, zero-padded (matrix-core path)
+    double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
     // matrix-core path, dense (k1, k2) layouts [N][LP][LP]:
@@ -201,7 +201,7 @@ struct S2Shape {
     }
     __host__ __device__ static int up4(int n) { return (n + 3) & ~3; }
     // per-vortex size of the padded self table (both parities)
-    __host__ __device__ int spad() const { return 2 * RP * LDS; }
+    __host__ __device__ int spad() const { return 2 * RP * KA; }
     // rows of the dense alpha layout (zero rows beyond LP cover the k-steps of the self product)
     __host__ __device__ int LA() const { return LP + 16; }
 };
