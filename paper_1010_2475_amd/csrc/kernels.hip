@@ -1217,7 +1217,11 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         const View va_ = {sAl, 1, LDA}, vb_ = {sT0, LDB, 1};
         for (int t = wave; t < tr * tc; t += kSelfWaves) {
             const int r0 = (t / tc) * 16, c0 = (t % tc) * 16;
-            const dbl4 d = mfma_tile<kSelfKS>(lane, r0, c0, 0, ks, va_, vb_);
+            // alpha[m1][m2] = 0 for m1 + m2 > M: rows m2 >= r0 need m1' <= (M - r0 - p1) / 2
+            // only (the k-steps skipped would add exact zeros at the end of the sum)
+            const int nm = M - r0 - p1 >= 0 ? ((M - r0 - p1) >> 1) + 1 : 0;
+            const int kt = (nm + 3) >> 2;
+            const dbl4 d = mfma_tile<kSelfKS>(lane, r0, c0, 0, kt < ks ? kt : ks, va_, vb_);
 #pragma unroll
             for (int q = 0; q < 4; ++q) sQ[(r0 + (lane >> 4) + 4 * q) * LDQ + c0 + (lane & 15)] = d[q];
         }
