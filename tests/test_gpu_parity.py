@@ -376,6 +376,36 @@ def test_graph_replay_batch_matches_direct_launches(env, M, prec):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_workspace_reuse_across_orders(env, prec):
+    """A stream's workspace serves every order from one allocation, laid out
+    anew for each order.  Order 33 stepped before and after an order-40 solve
+    on the same stream (the allocation grown for 40, then laid out for 33) gives
+    the same bits."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    big = wl.single_random(M=40, Re=500.0, seed=3)
+    small = wl.single_random(M=33, Re=800.0, seed=4)
+    s = torch.cuda.Stream()
+    out = []
+    with torch.cuda.stream(s):
+        for q in range(2):
+            if q == 1:
+                Xb = torch.tensor(big.x, device=dev)
+                Mb = torch.tensor(big.mom, device=dev)
+                print("workspace reuse: order 40 prec=%d" % prec, flush=True)
+                mm.step(big.M, big.nu, big.lam0, 0.0, 2e-3, 12, Xb, Mb, prec, stream=s)
+            X = torch.tensor(small.x, device=dev)
+            Mo = torch.tensor(small.mom, device=dev)
+            print("workspace reuse: order 33 prec=%d pass %d" % (prec, q), flush=True)
+            mm.step(small.M, small.nu, small.lam0, 0.0, 2e-3, 12, X, Mo, prec, stream=s)
+            mm.sync(s)
+            out.append(Mo.cpu().numpy())
+    assert np.all(np.isfinite(out[0]))
+    assert np.array_equal(out[0], out[1])
+
+
 def test_large_order_step_matches_oracle(env, orc):
     """Order 12, two RK4 steps of one vortex against the oracle's RK4."""
     from paper_1010_2475_amd import workloads as wl
