@@ -14,6 +14,14 @@ namespace mmvm {
 // most w/(P+k+1) <= P/(P+k+1), so 56 terms reach double precision for P <= 18
 constexpr int kSeriesTerms = 56;
 
+// 1/P! as the product 1/2 * 1/3 * ... * 1/P, each factor and product rounded
+constexpr double pair_inv_factorial(int P)
+{
+    double r = 1.0;
+    for (int f = 2; f <= P; ++f) r *= 1.0 / (double)f;
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // pair velocity-derivative table.
 //
@@ -43,8 +51,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
                                                           const double* __restrict__ lam2, const R* __restrict__ aT,
                                                           const double* __restrict__ kap0,
                                                           const double* __restrict__ kap1,
-                                                          const double* __restrict__ hol,
-                                                          const double* __restrict__ rcp, double* __restrict__ spair)
+                                                          const double* __restrict__ hol, double* __restrict__ spair)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -85,27 +92,26 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
         // gamma function), by the downward recurrence g_n = w g_{n+1} + e^{-w}/n!
         // from g_P:  w <= P: g_P = e^{-w} sum_k w^k/(P+k)!  (fixed-length Horner);
         //            w >  P: g_P = (1 - e^{-w} sum_{k<P} w^k/k!) / w^P.
+        // (the reciprocals 1/n are compile-time constants: no table loads in
+        // these dependent chains)
         double gsr[P + 1];
         {
-            double ifP = 1.0;  // 1/P!
-            for (int f = 2; f <= P; ++f) ifP *= rcp[f];
+            constexpr double ifP = pair_inv_factorial(P);  // 1/P!
             double gP;
             if (w <= (double)P) {
                 double term = ifP, sum = 0.0;
-#pragma unroll 1
-                for (int k = 0; k < kSeriesTerms; ++k) {
+                sfor<0, kSeriesTerms>([&](auto k) {
                     sum += term;
-                    term *= w * rcp[P + k + 1];
-                }
+                    term *= w * (1.0 / (double)(P + k + 1));
+                });
                 gP = E * sum;
             } else {
                 double sm = 0.0, term = 1.0, wp = 1.0;
-#pragma unroll 1
-                for (int k = 0; k < P; ++k) {
+                sfor<0, P>([&](auto k) {
                     sm += term;
-                    term *= w * rcp[k + 1];
+                    term *= w * (1.0 / (double)(k + 1));
                     wp *= w;
-                }
+                });
                 gP = (1.0 - E * sm) / wp;
             }
             gsr[P] = gP;
@@ -245,10 +251,10 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;
     if (f32)
         launch_kernel((k_pair<M, float>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT32[cur], T.kap0, T.kap1, T.hol, T.rcp, B.s_pair);
+                      B.alphaT32[cur], T.kap0, T.kap1, T.hol, B.s_pair);
     else
         launch_kernel((k_pair<M, double>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT[cur], T.kap0, T.kap1, T.hol, T.rcp, B.s_pair);
+                      B.alphaT[cur], T.kap0, T.kap1, T.hol, B.s_pair);
     return hipGetLastError();
 }
 
