@@ -14,6 +14,10 @@ namespace mmvm {
 // most w/(P+k+1) <= P/(P+k+1), so 56 terms reach double precision for P <= 18
 constexpr int kSeriesTerms = 56;
 
+// the edge coefficients kappa_e[n][c] and hol[n] of every shell n <= 18 as
+// constants (written by gen_pair_consts.py; the same values as the host tables)
+#include "pair_consts.inc"
+
 // 1/P! as the product 1/2 * 1/3 * ... * 1/P, each factor and product rounded
 constexpr double pair_inv_factorial(int P)
 {
@@ -49,9 +53,7 @@ constexpr double pair_inv_factorial(int P)
 template <int M, typename R>
 __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, const double* __restrict__ xs,
                                                           const double* __restrict__ lam2, const R* __restrict__ aT,
-                                                          const double* __restrict__ kap0,
-                                                          const double* __restrict__ kap1,
-                                                          const double* __restrict__ hol, double* __restrict__ spair)
+                                                          double* __restrict__ spair)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     constexpr int HN = P >= 2 ? P - 1 : 1;
     constexpr bool F32 = std::is_same<R, float>::value;
     constexpr double kInvPi = 0.318309886183790671537767526745;
+    static_assert(P <= kPairConstShells, "edge coefficients of every shell");
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tpb = (blockDim.x >> 6) / split;
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
                 zr = nr;
                 zi = ni;
             }
-            const double hr = hol[n] * gsr[n] * zr, hi = hol[n] * gsr[n] * zi;
+            const double hr = kPairHol[n] * gsr[n] * zr, hi = kPairHol[n] * gsr[n] * zi;
             // 2 Re(i^n h), 2 Re(i^{n-1} h)
             double e0, e1v;
             if constexpr (n % 4 == 0) { e0 = hr; e1v = hi; }
@@ -175,8 +178,8 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
             if constexpr (n >= 2) {
                 sfor<0, n - 1>([&](auto cc) {
                     prod[cc] = h1[cc] * h2[n - 2 - cc];
-                    p0 += (R)kap0[n * (P + 1) + cc] * prod[cc];
-                    p1 += (R)kap1[n * (P + 1) + cc] * prod[cc];
+                    p0 += (R)kPairKappa0[n][cc] * prod[cc];
+                    p1 += (R)kPairKappa1[n][cc] * prod[cc];
                 });
             }
             psi[0] = p0;
@@ -251,10 +254,10 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;
     if (f32)
         launch_kernel((k_pair<M, float>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT32[cur], T.kap0, T.kap1, T.hol, B.s_pair);
+                      B.alphaT32[cur], B.s_pair);
     else
         launch_kernel((k_pair<M, double>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT[cur], T.kap0, T.kap1, T.hol, B.s_pair);
+                      B.alphaT[cur], B.s_pair);
     return hipGetLastError();
 }
 

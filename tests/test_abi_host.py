@@ -139,3 +139,19 @@ def test_factor_tables(mm, M):
               if (i <= l and i <= k - 1) else 0)
         for got, ref in ((F[0, k, l, i], f0), (F[1, k, l, i], f1)):
             assert (got == 0.0 and ref == 0) or abs(got - ref) <= 1e-15 * ref
+
+
+def test_pair_constants_file_is_generated(tmp_path):
+    """The pair kernel's edge-coefficient constants are exactly what their
+    generator writes (no hand edits)."""
+    import importlib.util
+    import shutil
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "paper_1010_2475_amd", "csrc")
+    gen = os.path.join(here, "gen_pair_consts.py")
+    shutil.copy(gen, tmp_path / "gen_pair_consts.py")
+    spec = importlib.util.spec_from_file_location("gen_pair_consts_copy", tmp_path / "gen_pair_consts.py")
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.main()  # writes pair_consts.inc beside the copy
+    with open(tmp_path / "pair_consts.inc") as f, open(os.path.join(here, "pair_consts.inc")) as g:
+        assert f.read() == g.read()
