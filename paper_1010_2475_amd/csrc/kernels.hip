@@ -725,6 +725,8 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
         }
         if (pass == 0) {
             const int imax = l1 < k1 - 1 ? l1 : k1 - 1;
+            // unrolled: the table loads of two terms issue together (same order of sums)
+#pragma unroll 2
             for (int i = 0; i <= imax; ++i) {
                 const int r = (k1 + l1 - 2 * i - 1 - par) >> 1;
                 const dd f = dd_mul_d(dd_make(fdh[fs * i], fdl[fs * i]), bn[i]);
@@ -735,6 +737,7 @@ __global__ __launch_bounds__(kDDThreads) void k_stage2_dd(DevTables T, StageBufs
         } else {
             const int imax = l1 < k1 ? l1 : k1;
             const int i0 = k1 + l1 + 1 > GM ? 1 : 0;
+#pragma unroll 2
             for (int i = i0; i <= imax; ++i) {
                 const int r = (k1 + l1 - 2 * i + 1 - par) >> 1;
                 const dd f = dd_mul_d(dd_make(fdh[fs * i], fdl[fs * i]), bn[i]);
