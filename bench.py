@@ -65,9 +65,9 @@ def self_flops(M):
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
 # and written per launch; FETCH_SIZE read 131083 KiB, WRITE_SIZE 262146 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3243.9, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.5,
-                  "write_scale": 262144.0 / 262146.9,
-                  "sources_sha256": {"kernels.hip": "b5099015b832d7fc4d6c93aa8b8df788f59a9c80087f6ae7618457efddaf6fae",
+TRAFFIC_STAGE2 = {"fetch_kib": 3243.8, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.6,
+                  "write_scale": 262144.0 / 262146.5,
+                  "sources_sha256": {"kernels.hip": "85f4cda03884d4dd1e8d30bb3f0718e51585ca86d4444e2e3a6db028798c9fb1",
                                      "kernels.hpp": "7eab1c200a65f53cc9b7280e7af9fff0a39ee427f48b7206bf1d854c16a9459a"}}
 
 
