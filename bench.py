@@ -199,6 +199,39 @@ def rhs_error(mm, torch, orc, w, x, mom, prec, t, rows):
     return max(abs(g[r] - ref[i]) * n[r] for i, r in enumerate(rows)) / np.abs(g * n).max()
 
 
+ONLY = {"single_quadrupole": "single_quadrupole", "single_random": "single_random",
+        "random_multi": "random_multi", "two_clusters": "two_clusters"}
+
+
+def only_leg(args):
+    """One workload alone, stepped with the state resident on the device: W
+    warmup steps, then K timed steps (for kernel traces and counters)."""
+    import torch
+    from paper_1010_2475_amd import mmvm as mm
+    from paper_1010_2475_amd import workloads as wl
+    w = getattr(wl, ONLY[args.only])()
+    dev = torch.device("cuda:0")
+    precs = [args.precision] if args.precision else ["mixed", "fp64"]
+    out = {"workload": args.only, "N": w.N, "M": w.M, "steps": args.steps, "warmup": args.warmup}
+    for pname in precs:
+        prec = mm.MIXED if pname == "mixed" else mm.FP64
+        X = torch.tensor(w.x, device=dev)
+        Mo = torch.tensor(w.mom, device=dev)
+        print("%s %s: %d warmup + %d steps" % (args.only, pname, args.warmup, args.steps), file=sys.stderr,
+              flush=True)
+        if args.warmup:
+            mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, args.warmup, X, Mo, prec)
+        mm.sync()
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        mm.step(w.M, w.nu, w.lam0, args.warmup * w.dt, w.dt, args.steps, X, Mo, prec)
+        mm.sync()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t_a
+        out[pname] = {"moment_updates_per_s": w.N * w.K * args.steps / secs, "ms_per_step": 1e3 * secs / args.steps}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,7 +246,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy (y = 1.0 * x over 256 MiB, five launches), the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes, and exit")
+    ap.add_argument("--only", choices=sorted(ONLY), default=None,
+                    help="time one workload alone (both precisions unless --precision) and print its line; for "
+                         "profiling one path under rocprofv3")
+    ap.add_argument("--precision", choices=("mixed", "fp64"), default=None)
     args = ap.parse_args()
+    if args.only:
+        only_leg(args)
+        return
     if args.copy_calibration:
         import torch
         n = 32 * 1024 * 1024  # doubles: 256 MiB read and 256 MiB written per launch

@@ -104,6 +104,15 @@ void dd_task_lists(int M, std::vector<int32_t>& la, std::vector<int32_t>& lc)
 
 }  // namespace
 
+const DevTables* find_device_tables(int M)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_dev_tables.find(std::make_pair(dev, M));
+    return it == g_dev_tables.end() ? nullptr : &it->second->t;
+}
+
 mmvm_status device_tables(int M, const DevTables** out)
 {
     int dev = 0;
@@ -309,12 +318,52 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 }
 }  // namespace
 
-size_t Workspace::bytes_for(int N_, int M_, bool need_dd, bool solo) { return layout_for(N_, M_, need_dd, solo).total; }
+size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs* out, DevClock** clock,
+                    double** par)
+{
+    const Layout L = layout_for(N_, M_, need_dd, solo);
+    if (!b) return L.total;
+    StageBufs& bufs = *out;
+    bufs = StageBufs{};
+    bufs.N = N_;
+    bufs.interact = (!solo && N_ > 1) ? 1 : 0;
+    bufs.lam0sq = (const double*)(b + L.lam0);
+    bufs.nuv = (const double*)(b + L.lam0) + N_;
+    bufs.xs = (double*)(b + L.xs);
+    bufs.ys = (double*)(b + L.ys);
+    bufs.accx = (double*)(b + L.accx);
+    bufs.accm = (double*)(b + L.accm);
+    const bool mx = stage2_uses_mfma(M_, false, solo);
+    for (int q = 0; q < 2; ++q) {
+        bufs.lam2[q] = (double*)(b + L.lam2[q]);
+        bufs.alpha[q] = (double*)(b + L.alpha[q]);
+        bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
+        bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
+        bufs.alphaD[q] = mx ? (double*)(b + L.alphaD[q]) : nullptr;
+        bufs.alphaS[q] = mx ? (double*)(b + L.alphaS[q]) : nullptr;
+    }
+    bufs.s_self = (double*)(b + L.sself);
+    bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
+    bufs.s_pair = (double*)(b + L.spair);
+    bufs.s_pad = (double*)(b + L.spad);
+    for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
+    bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
+    bufs.gpartD = mx ? (double*)(b + L.gpartd) : nullptr;
+    bufs.gpart = (double*)(b + L.gpart);
+    bufs.flag = (int*)(b + L.flag);
+    if (clock) *clock = (DevClock*)(b + L.clock);
+    if (par) *par = (double*)(b + L.lam0);
+    return L.total;
+}
+
+size_t Workspace::bytes_for(int N_, int M_, bool need_dd, bool solo)
+{
+    return stage_layout(nullptr, N_, M_, need_dd, solo, nullptr, nullptr, nullptr);
+}
 
 mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, bool solo, hipStream_t st)
 {
-    const Layout L = layout_for(N_, M_, need_dd, solo);
-    const size_t need = L.total;
+    const size_t need = bytes_for(N_, M_, need_dd, solo);
     if (need > bytes) {
         // the old buffer may still be used by queued work on this stream
         if (base) {
@@ -341,39 +390,8 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, bool solo, hipStream
     }
     N = N_;
     M = M_;
-    char* b = base;
-    bufs.N = N_;
-    bufs.interact = (!solo && N_ > 1) ? 1 : 0;
-    bufs.lam0sq = (const double*)(b + L.lam0);
-    bufs.nuv = (const double*)(b + L.lam0) + N_;
-    bufs.xs = (double*)(b + L.xs);
-    bufs.ys = (double*)(b + L.ys);
-    bufs.accx = (double*)(b + L.accx);
-    bufs.accm = (double*)(b + L.accm);
-    for (int q = 0; q < 2; ++q) {
-        bufs.lam2[q] = (double*)(b + L.lam2[q]);
-        bufs.alpha[q] = (double*)(b + L.alpha[q]);
-        bufs.alphaT[q] = (double*)(b + L.alphaT[q]);
-        bufs.alphaT32[q] = (float*)(b + L.alphaT32[q]);
-        const bool mx = stage2_uses_mfma(M_, false, solo);
-        bufs.alphaD[q] = mx ? (double*)(b + L.alphaD[q]) : nullptr;
-        bufs.alphaS[q] = mx ? (double*)(b + L.alphaS[q]) : nullptr;
-    }
-    bufs.s_self = (double*)(b + L.sself);
-    bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
-    bufs.s_pair = (double*)(b + L.spair);
-    bufs.s_pad = (double*)(b + L.spad);
-    {
-        const bool mx = stage2_uses_mfma(M_, false, solo);
-        for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
-        bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
-        bufs.gpartD = mx ? (double*)(b + L.gpartd) : nullptr;
-    }
-    bufs.gpart = (double*)(b + L.gpart);
-    bufs.flag = (int*)(b + L.flag);
+    stage_layout(base, N_, M_, need_dd, solo, &bufs, &clock, &par_dev);
     flag_ptr = bufs.flag;
-    clock = (DevClock*)(b + L.clock);
-    par_dev = (double*)(b + L.lam0);
     return MMVM_OK;
 }
 
@@ -444,45 +462,62 @@ static mmvm_status hip_status(hipError_t e, const char* where)
     return e == hipErrorOutOfMemory ? MMVM_ENOMEM : MMVM_EDEVICE;
 }
 
-// the kernels of one stage whose inputs are in buffer A.cur (prep already ran)
-mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st)
+// the kernels of one stage whose inputs are in buffer A.cur (prep already ran);
+// shape: the pair kernel's launch shape, or null for the autotuner's
+mmvm_status run_stage_bufs(const DevTables& T, const StageBufs& B, mmvm_precision prec, const StageArgs& A,
+                           hipStream_t st, const PairShape* shape)
 {
-    const bool pair = W.bufs.interact != 0;
+    const bool pair = B.interact != 0;
     const bool f32 = prec == MMVM_MIXED;
     const bool dd = use_dd(T.M, prec);
     hipError_t e;
     void* tk;
-    if (!stage2_fuses_self(T.M, dd, !W.bufs.interact)) {
+    if (!stage2_fuses_self(T.M, dd, !B.interact)) {
         tk = timing_begin(st);
-        e = launch_self(T, W.bufs, A.cur, dd, st);
+        e = launch_self(T, B, A.cur, dd, st);
         timing_end(tk, "self", st);
         if (e != hipSuccess) return hip_status(e, "k_self launch");
     }
     if (pair) {
         tk = timing_begin(st);
-        e = launch_pair(T, W.bufs, A.cur, f32, st);
+        e = shape ? launch_pair_shape(T, B, A.cur, f32, *shape, st) : launch_pair(T, B, A.cur, f32, st);
         timing_end(tk, "pair", st);
         if (e != hipSuccess) return hip_status(e, "k_pair launch");
+        if (dd || stage2_uses_mfma(T.M, dd, false)) {
+            e = launch_pair_into_stage2(T, B, dd, st);
+            if (e != hipSuccess) return hip_status(e, "k_pair_into_stage2 launch");
+        }
     }
     tk = timing_begin(st);
-    e = launch_stage2(T, W.bufs, A, dd, st);
+    e = launch_stage2(T, B, A, dd, st);
     timing_end(tk, "stage2", st);
     if (e != hipSuccess) return hip_status(e, "k_stage2 launch");
-    if (!stage2_needs_emit(T.M, dd, !W.bufs.interact)) return MMVM_OK;
+    if (!stage2_needs_emit(T.M, dd, !B.interact)) return MMVM_OK;
     tk = timing_begin(st);
-    e = launch_emit(T, W.bufs, A, dd, st);
+    e = launch_emit(T, B, A, dd, st);
     timing_end(tk, "emit", st);
     return hip_status(e, "k_emit launch");
 }
 
+mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st)
+{
+    return run_stage_bufs(T, W.bufs, prec, A, st, nullptr);
+}
+
 // stage inputs (xin, min_) at time t -> buffer `cur`
+mmvm_status run_prep_bufs(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
+                          double t, mmvm_precision prec, hipStream_t st)
+{
+    void* tk = timing_begin(st);
+    hipError_t e = launch_prep(T, B, cur, xin, min_, t, B.interact != 0, prec == MMVM_MIXED, st);
+    timing_end(tk, "prep", st);
+    return hip_status(e, "k_prep launch");
+}
+
 mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
                      mmvm_precision prec, hipStream_t st)
 {
-    void* tk = timing_begin(st);
-    hipError_t e = launch_prep(T, W.bufs, cur, xin, min_, t, W.bufs.interact != 0, prec == MMVM_MIXED, st);
-    timing_end(tk, "prep", st);
-    return hip_status(e, "k_prep launch");
+    return run_prep_bufs(T, W.bufs, cur, xin, min_, t, prec, st);
 }
 
 }  // namespace mmvm

@@ -53,6 +53,14 @@ struct Workspace {
 };
 
 mmvm_status device_tables(int M, const DevTables** out);
+// the tables of order M on the current device if they were built, else null (builds nothing)
+const DevTables* find_device_tables(int M);
+// Lays out the workspace regions of one solve of N vortices at order M from
+// `base` (256-byte aligned regions; the error flag first) and binds them to
+// *bufs, *clock and *par ([2N]: lambda_{j,0}^2, then nu_j); returns the bytes
+// needed.  With base == nullptr it only returns the size.
+size_t stage_layout(char* base, int N, int M, bool need_dd, bool solo, StageBufs* bufs, DevClock** clock,
+                    double** par);
 
 // per-kernel timing (mmvm_timing_enable); no-ops when disabled
 bool timing_on();
@@ -67,6 +75,13 @@ bool use_dd(int M, mmvm_precision prec);
 mmvm_status run_prep(const DevTables& T, Workspace& W, int cur, const double* xin, const double* min_, double t,
                      mmvm_precision prec, hipStream_t st);
 mmvm_status run_stage(const DevTables& T, Workspace& W, mmvm_precision prec, const StageArgs& A, hipStream_t st);
+// the same on explicit buffers; shape fixes the pair kernel's launch shape (null: the autotuner's)
+mmvm_status run_prep_bufs(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
+                          double t, mmvm_precision prec, hipStream_t st);
+mmvm_status run_stage_bufs(const DevTables& T, const StageBufs& B, mmvm_precision prec, const StageArgs& A,
+                           hipStream_t st, const PairShape* shape);
+// the pair-kernel shape already chosen for (order, precision, N) in this process, or the default (never tunes)
+PairShape pair_shape_known(int M, bool f32, int N);
 mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, int64_t nsteps, double* x,
                       double* mom, mmvm_precision prec, hipStream_t st);
 

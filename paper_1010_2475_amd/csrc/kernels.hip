@@ -28,7 +28,7 @@ namespace mmvm {
 // runtime keeps the attribute per device.  Later calls only look the result
 // up, so a launch that a caller captures into a graph makes no attribute call
 // once an uncaptured launch on that device has made it.
-static hipError_t lds_limit_once(const void* fn, size_t bytes, const char* what)
+hipError_t lds_limit_once(const void* fn, size_t bytes, const char* what)
 {
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, hipError_t> done;
@@ -376,10 +376,11 @@ hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd,
 template <int M>
 hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
 
-bool pair_order_supported(int M) { return M >= 0 && M <= kMaxPairOrder; }
+bool pair_order_supported(int M) { return M >= 0 && M <= MMVM_MAX_ORDER; }
 
 hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
+    if (T.M > kMaxPairOrder) return launch_pair_gen(T, B, cur, st);  // any order, FP64
     switch (T.M) {
     case 0: return launch_pair_M<0>(T, B, cur, f32, sh, st);
     case 1: return launch_pair_M<1>(T, B, cur, f32, sh, st);
@@ -394,7 +395,53 @@ hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bo
 
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
 {
+    if (T.M > kMaxPairOrder) return launch_pair_gen(T, B, cur, st);
     return launch_pair_shape(T, B, cur, f32, pair_shape_for(T, B, cur, f32, st), st);
+}
+
+// The pair table joins the self table as the operand of the large-order stage
+// 2 (interacting vortices): S = S_self + S_pair.
+//   padded matrix-core layout: s_pad[j][par][g2][r] with g1 = par + 2r;
+//   double-double layout: (s_self, s_self_lo) += s_pair, an exact two-sum plus
+//   the low word.
+__global__ __launch_bounds__(256) void k_pair_into_pad(StageBufs B, int GM, int KG, int KA, int RP)
+{
+    const long total = (long)B.N * KG;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / KG), g = (int)(idx - (long)j * KG);
+        if (g == 0) continue;
+        const int gs = shell_of(g), g2 = g - gs * (gs + 1) / 2, g1 = gs - g2;
+        double* o = B.s_pad + (((long)j * 2 + (g1 & 1)) * KA + g2) * RP + (g1 >> 1);
+        *o += B.s_pair[idx];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pair_into_dd(StageBufs B, int KG)
+{
+    const long total = (long)B.N * KG;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        if (idx - (idx / KG) * KG == 0) continue;
+        const dd t = two_sum(B.s_self[idx], B.s_pair[idx]);
+        const dd v = quick_two_sum(t.hi, t.lo + B.s_self_lo[idx]);
+        B.s_self[idx] = v.hi;
+        B.s_self_lo[idx] = v.lo;
+    }
+}
+
+hipError_t launch_pair_into_stage2(const DevTables& T, const StageBufs& B, bool dd, hipStream_t st)
+{
+    const long total = (long)B.N * T.KG;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (dd) {
+        if (!B.s_self_lo) return hipErrorInvalidValue;
+        launch_kernel(k_pair_into_dd, dim3(blocks), dim3(256), 0, st, B, T.KG);
+    } else {
+        if (!B.s_pad) return hipErrorInvalidValue;
+        const S2Shape sh(T.M, 0);
+        launch_kernel(k_pair_into_pad, dim3(blocks), dim3(256), 0, st, B, T.GM, T.KG, sh.KA, sh.RP);
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1748,7 +1795,7 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
     const int M1 = T.M + 1;
     dim3 grid(4 * M1, B.N);
     if (!use_dd) {
-        if (!stage2_uses_mfma(T.M, use_dd, !B.interact) || B.interact) return hipErrorInvalidValue;
+        if (!stage2_uses_mfma(T.M, use_dd, !B.interact)) return hipErrorInvalidValue;
         const size_t shmem = sizeof(double) * (size_t)s2m_lds_doubles(T.M);
         // the limit is the largest order's size for every order
         const size_t most = sizeof(double) * (size_t)s2m_lds_doubles(kS2MaxOrder);
@@ -1759,8 +1806,8 @@ hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs
         launch_kernel(k_stage2_mfma, grid, dim3(kS2Threads), shmem, st, T, B, A);
         return hipGetLastError();
     }
-    // single vortices only; the fill is sized for kDDThreads threads and orders <= MMVM_MAX_ORDER
-    if (B.interact || !B.s_self_lo || T.M > MMVM_MAX_ORDER) return hipErrorInvalidValue;
+    // the fill is sized for kDDThreads threads and orders <= MMVM_MAX_ORDER
+    if (!B.s_self_lo || T.M > MMVM_MAX_ORDER) return hipErrorInvalidValue;
     // the workgroups fit one round at one per CU: stage step C's tables in LDS;
     // more: the smaller layout, two workgroups per CU
     const bool ctab = 4 * M1 * B.N <= kDDOneRound;

@@ -219,9 +219,16 @@ struct T0Shape {
     }
 };
 
-// the pair kernel is compiled for orders 0..kMaxPairOrder
+// the unrolled pair kernel is compiled for orders 0..kMaxPairOrder; above, the
+// runtime-order kernel (pair_gen.hip) runs, in FP64 for both precisions
 constexpr int kMaxPairOrder = 6;
 bool pair_order_supported(int M);
+hipError_t launch_pair_gen(const DevTables& T, const StageBufs& B, int cur, hipStream_t st);
+// interacting vortices above the small orders: S_pair added into the operand of
+// the matrix-core (padded) or double-double stage 2
+hipError_t launch_pair_into_stage2(const DevTables& T, const StageBufs& B, bool dd, hipStream_t st);
+// raises a kernel's dynamic-LDS limit to `bytes`, once per (kernel, device)
+hipError_t lds_limit_once(const void* fn, size_t bytes, const char* what);
 
 // Kernel timing: while a slot is set on the calling thread, the next kernel
 // launched through launch_kernel carries the slot's events, which the runtime

@@ -195,10 +195,13 @@ static mmvm_status run_steps_fused(const DevTables& T, Workspace& W, const Stage
         }
     }
     int64_t n = 1;
-    if (e == hipSuccess && nsteps - 1 >= kGraphSteps && graphs_enabled() && !timing_on() && W.clock) {
+    // The graph is captured by the first call of its key whatever its length,
+    // so that a short first call (a warmup, a server's first chunk) leaves the
+    // capture behind it; it is replayed once a call has enough steps.
+    if (e == hipSuccess && graphs_enabled() && !timing_on() && W.clock) {
         hipGraphExec_t g = stepping_graph(T, W, A, kGraphMFMA, st);
-        if (g) {
-            const int64_t reps = (nsteps - 1) / kGraphSteps;
+        const int64_t reps = (nsteps - 1) / kGraphSteps;
+        if (g && reps > 0) {
             e = launch_set_clock(W.clock, t0, 1, st);
             for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(g, st);
             if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
@@ -255,10 +258,10 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, in
     // the double-double path (single vortices): step 0 direct, then replays
     // of a kDDGraphSteps-step graph on a clock that starts at step 0, then
     // the remaining steps direct
-    const bool dd_graph = use_dd(T.M, prec) && !W.bufs.interact && nsteps - 1 >= kGraphMinSteps &&
-                          graphs_enabled() && !timing_on() && W.clock;
+    const bool dd_graph = use_dd(T.M, prec) && !W.bufs.interact && graphs_enabled() && !timing_on() && W.clock;
+    if (dd_graph && nsteps - 1 < kGraphMinSteps) (void)stepping_graph(T, W, A, kGraphDD, st);  // captured for later calls
     for (int64_t n = 0; n < nsteps; ++n) {
-        if (n == 1 && dd_graph) {
+        if (n == 1 && dd_graph && nsteps - 1 >= kGraphMinSteps) {
             hipGraphExec_t g = stepping_graph(T, W, A, kGraphDD, st);
             if (g) {
                 const int64_t reps = (nsteps - 1) / kDDGraphSteps;

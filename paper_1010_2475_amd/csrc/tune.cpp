@@ -64,9 +64,18 @@ double time_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, Pair
 
 }  // namespace
 
+PairShape pair_shape_known(int M, bool f32, int N)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!enabled_locked()) return PairShape();
+    auto it = g_pair.find(std::make_tuple(M, f32 ? 1 : 0, bucket(N)));
+    return it == g_pair.end() ? PairShape() : it->second.shape;
+}
+
 PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
 {
     const PairShape def;
+    if (T.M > kMaxPairOrder) return def;  // the runtime-order kernel has one shape
     std::lock_guard<std::mutex> lk(g_mu);
     if (!enabled_locked()) return def;
     const auto key = std::make_tuple(T.M, f32 ? 1 : 0, bucket(B.N));

@@ -34,11 +34,17 @@ def _nk(M, lam):
     return wl.orthonormal_scale(M, lam)
 
 
-def normwise(M, lam_t, ref, got):
+def normwise(M, lam_t, ref, got, gam=None, xdot=None):
+    """With gam and xdot (per vortex), the scale of a vortex is at least the
+    size |Gamma_j| |xdot_j| of the drift and pair terms that cancel in the
+    first-moment rates (exactly zero when the first moments vanish, eq:xjdef),
+    in orthonormal units; otherwise max_k |n_k ref_k|."""
     worst = 0.0
     for j in range(ref.shape[0]):
         n = _nk(M, lam_t[j])
         den = np.abs(ref[j] * n).max()
+        if gam is not None and M >= 1:
+            den = max(den, abs(gam[j]) * np.abs(xdot[j]).max() * n[1])
         num = np.abs((got[j] - ref[j]) * n).max()
         worst = max(worst, num / den if den > 0 else num)
     return worst
@@ -106,7 +112,11 @@ def structure(w, seed, amp=0.05):
 # ---------------------------------------------------------------------------
 # right-hand side, small cases covering several tiles, ragged tails and edges
 # ---------------------------------------------------------------------------
-CASES = [(1, 0), (1, 1), (1, 3), (1, 6), (1, 7), (1, 8), (1, 10), (2, 0), (2, 2), (3, 4), (5, 6), (67, 2), (130, 3)]
+CASES = [(1, 0), (1, 1), (1, 3), (1, 6), (1, 7), (1, 8), (1, 10), (2, 0), (2, 1), (4, 1), (7, 1), (2, 2), (3, 4),
+         (5, 6), (67, 2), (130, 3),
+         # multi-vortex orders above the unrolled pair kernel (runtime-order pair kernel):
+         # the small fused stage 2 (7-10), the matrix-core stage 2 (11 and up)
+         (2, 7), (3, 8), (3, 10), (2, 12), (9, 9)]
 
 
 @pytest.mark.parametrize("N,M", CASES)
@@ -131,7 +141,8 @@ def test_rhs_matches_oracle(env, orc, N, M, prec):
         dx_g, dm_g, lam_t = dx_g[rows], dm_g[rows], lam_t[rows]
     tol = FP64_TOL if prec == 0 else MIXED_TOL
     assert np.all(dm_g[:, 0] == 0.0)
-    assert normwise(M, lam_t, dm_r, dm_g) <= tol
+    gam = w.mom[:, 0] if rows is None else w.mom[rows, 0]
+    assert normwise(M, lam_t, dm_r, dm_g, gam, dx_r) <= tol
     if N > 1:
         assert np.abs(dx_g - dx_r).max() <= tol * max(1.0, np.abs(dx_r).max())
     else:
@@ -191,7 +202,7 @@ def test_nonfinite_is_reported(env):
 # ---------------------------------------------------------------------------
 # RK4 stepping
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("N,M,steps", [(1, 6, 20), (3, 3, 10), (4, 2, 25)])
+@pytest.mark.parametrize("N,M,steps", [(1, 6, 20), (3, 3, 10), (4, 2, 25), (2, 8, 5), (2, 12, 3)])
 def test_step_matches_oracle(env, orc, N, M, steps):
     w = rand_workload(200 + N, N, M)
     w.dt = 2e-3
@@ -473,7 +484,7 @@ def test_single_random_order40_sampled_rows(env, orc, prec, tol):
     d, _ = orc.rhs_rows(40, w.nu, w.lam0, t, w.x, w.mom, [0] * len(rows), rows)
     lam = math.sqrt(w.lam0[0] ** 2 + 4 * w.nu * t)
     n = _nk(40, lam)
-    scale = np.abs(dm_g[0] * n).max()
+    scale = max(abs(d[i]) * n[r] for i, r in enumerate(rows))  # the oracle's rows set the scale
     err = max(abs(dm_g[0, r] - d[i]) * n[r] for i, r in enumerate(rows)) / scale
     assert err <= tol, err
     assert dm_g[0, 0] == 0.0
@@ -497,7 +508,7 @@ def test_single_particle_orders_sampled_rows(env, orc, M, prec):
     d, _ = orc.rhs_rows(M, w.nu, w.lam0, t, w.x, w.mom, [0] * len(rows), rows)
     lam = math.sqrt(w.lam0[0] ** 2 + 4 * w.nu * t)
     n = _nk(M, lam)
-    scale = np.abs(dm_g[0] * n).max()
+    scale = max(abs(d[i]) * n[r] for i, r in enumerate(rows))  # the oracle's rows set the scale
     err = max(abs(dm_g[0, r] - d[i]) * n[r] for i, r in enumerate(rows)) / scale
     tol = FP64_TOL if (M <= 24 or prec == 0) else 1e-9
     assert err <= tol, err
@@ -593,3 +604,32 @@ def test_two_clusters_4096_sampled(env, orc, prec, tol):
     G = w.mom[:, 0]
     assert np.all(dm_g[:, 0] == 0.0)
     assert abs((G[:, None] * dx_g).sum(0)).max() <= tol * np.abs(G[:, None] * dx_g).sum()
+
+
+@pytest.mark.parametrize("N,M,prec", [(2, 20, 0), (2, 20, 1), (3, 16, 1), (2, 30, 0), (2, 40, 1)])
+def test_multi_vortex_high_orders_sampled_rows(env, orc, N, M, prec):
+    """Interacting vortices at high orders: the runtime-order pair kernel (every
+    shell up to 3M generated in LDS) feeding the matrix-core stage 2 (FP64 up to
+    order 24, the mixed path at every order) or the double-double stage 2 (FP64
+    above order 24), on rows spread over the shells of every vortex."""
+    from paper_1010_2475_amd import workloads as wl
+    w = rand_workload(700 + N + M, N, M, spread=1.2)
+    t = 0.13
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    h = M // 2
+    ks = sorted({wl.index(1, 1), wl.index(2, 0), wl.index(0, M), wl.index(M, 0), wl.index(h, M - h),
+                 wl.index(3, 2), wl.index(M // 3, M // 3), wl.index(1, M - 1), wl.index(M - 2, 1)})
+    rj = [j for j in range(N) for _ in ks]
+    rk = [k for _ in range(N) for k in ks]
+    d, dxr = orc.rhs_rows(M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    tol = FP64_TOL if prec == 0 else MIXED_TOL
+    for j in range(N):
+        n = _nk(M, lam_t[j])
+        ref = d[j * len(ks):(j + 1) * len(ks)]
+        got = dm_g[j, ks]
+        scale = np.abs(ref * n[ks]).max()  # the oracle's rows set the scale
+        assert np.abs((got - ref) * n[ks]).max() <= tol * scale, (j, np.abs((got - ref) * n[ks]).max() / scale)
+    dx_r = dxr.reshape(N, len(ks), 2)[:, 0, :]
+    assert np.abs(dx_g - dx_r).max() <= tol * max(1.0, np.abs(dx_r).max())
+    assert np.all(dm_g[:, 0] == 0.0)

@@ -158,3 +158,43 @@ def test_concurrent_submitters(mm):
         assert np.all(np.isfinite(m)) and st["steps"] == w.steps
         assert np.array_equal(m[:, 0], w.mom[:, 0])
     srv.close()
+
+
+def _normwise(M, lam_t, ref, got):
+    from paper_1010_2475_amd import workloads as wl
+    worst = 0.0
+    for j in range(ref.shape[0]):
+        n = wl.orthonormal_scale(M, lam_t[j])
+        worst = max(worst, np.abs((got[j] - ref[j]) * n).max() / np.abs(ref[j] * n).max())
+    return worst
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
+def test_served_results_match_oracle(mm, orc, prec, tol):
+    """Requests served together (a multi-vortex and two single-vortex solves of
+    different orders, submitted while the others run) against the oracle's RK4
+    of each request alone."""
+    from paper_1010_2475_amd import workloads as wl
+    from test_gpu_parity import rand_workload
+    multi = rand_workload(81, 3, 3)
+    multi.dt, multi.steps = 2e-3, 12
+    single = wl.single_random(M=9, Re=300.0, seed=82, steps=15)
+    single.dt = 2e-3
+    big = wl.single_random(M=14, Re=900.0, seed=83, steps=10)
+    big.dt = 2e-3
+    reqs = [multi, single, big]
+    srv = mm.Server(1 << 30, 3)
+    tks = []
+    for w in reqs:
+        print("submit N=%d M=%d prec=%d" % (w.N, w.M, prec), flush=True)
+        tks.append(srv.submit(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom, prec))
+    srv.drain()
+    for w, tk in zip(reqs, tks):
+        x, m, st = srv.poll(tk, w.N, w.M)
+        x_r, m_r = orc.rk4(w.M, w.nu, w.lam0, 0.0, w.dt, w.steps, w.x, w.mom)
+        lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * w.steps * w.dt)
+        assert _normwise(w.M, lam_t, m_r, m) <= tol, (w.N, w.M)
+        assert np.abs(x - x_r).max() <= tol * max(1.0, np.abs(x_r).max())
+        assert np.array_equal(m[:, 0], w.mom[:, 0])
+        assert st["steps"] == w.steps
+    srv.close()

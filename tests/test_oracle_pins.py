@@ -414,3 +414,67 @@ def test_golden_quadrupole_initial_condition():
     # and the workload generator reproduces it
     w = wl.single_quadrupole(M=M, delta=delta)
     assert np.array_equal(w.mom[0], ref)
+
+
+# ---------------------------------------------------------------------------
+# The row entry point (the checker of every sampled-row GPU test) against the
+# full right-hand side: the same arithmetic per row, so equal bit for bit on
+# every (vortex, coefficient) row, including the centre velocity of each row.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,M,seed", [(3, 4, 71), (1, 9, 72), (4, 2, 73)])
+def test_rhs_rows_equals_full_rhs_bitwise(orc, N, M, seed):
+    rng = np.random.default_rng(seed)
+    x, mom, lam0 = _rand_state(rng, N, M, amp=0.2, spread=1.2)
+    nu, t = 3e-3, 0.41
+    dx, dm = orc.rhs(M, nu, lam0, t, x, mom)
+    K = wl.K_of(M)
+    rj = [j for j in range(N) for _ in range(K)]
+    rk = [k for _ in range(N) for k in range(K)]
+    d, dxr = orc.rhs_rows(M, nu, lam0, t, x, mom, rj, rk)
+    assert np.array_equal(d.reshape(N, K), dm)
+    assert np.array_equal(dxr.reshape(N, K, 2), np.repeat(dx[:, None, :], K, axis=1))
+    # a shuffled subset of rows, with repeats, gives the same values
+    perm = rng.permutation(N * K)[: max(1, N * K // 2)]
+    perm = np.concatenate([perm, perm[:3]])
+    d2, dx2 = orc.rhs_rows(M, nu, lam0, t, x, mom, [rj[i] for i in perm], [rk[i] for i in perm])
+    assert np.array_equal(d2, d[perm])
+    assert np.array_equal(dx2, dxr[perm])
+
+
+# ---------------------------------------------------------------------------
+# H^B at the total orders the multi-vortex contraction reaches (up to 3M - 1:
+# 17 at order 6, 23 at order 8, 35 at order 12), against 60- and 90-digit
+# numerical differentiation (mpmath) of V00, at w = |s|^2 / Lambda^2 = 0.01,
+# 1 and 10 (and 60, deep in the far field).
+# ---------------------------------------------------------------------------
+def _V00(comp, L2):
+    def f(x, y):
+        r2 = x * x + y * y
+        g = (1 - mp.exp(-r2 / L2)) / (2 * mp.pi * r2)
+        return -y * g if comp == 1 else x * g
+    return f
+
+
+@pytest.mark.parametrize("w", [0.01, 1.0, 10.0])
+def test_HB_high_orders_match_mpmath(orc, w):
+    mp.mp.dps = 60
+    L2 = 0.5
+    r = math.sqrt(w * L2)
+    s1, s2 = 0.6 * r, -0.8 * r
+    for (a1, a2) in [(10, 0), (0, 11), (3, 9), (7, 5), (13, 1), (2, 14), (8, 9), (0, 17), (17, 0)]:
+        for comp in (1, 2):
+            ref = float(mp.diff(_V00(comp, L2), (mp.mpf(s1), mp.mpf(s2)), (a1, a2)))
+            got = orc.HB(comp, a1, a2, s1, s2, L2)
+            assert abs(got - ref) <= 1e-13 * abs(ref), (w, comp, a1, a2, got, ref)
+
+
+@pytest.mark.parametrize("w", [0.01, 1.0, 10.0, 60.0])
+def test_HB_orders_23_and_35_match_mpmath(orc, w):
+    mp.mp.dps = 90
+    L2 = 0.37
+    r = math.sqrt(w * L2)
+    s1, s2 = -0.28 * r, 0.96 * r
+    for (a1, a2, comp) in [(23, 0, 2), (0, 23, 1), (21, 2, 1), (0, 35, 1), (35, 0, 2), (1, 34, 2)]:
+        ref = float(mp.diff(_V00(comp, L2), (mp.mpf(s1), mp.mpf(s2)), (a1, a2)))
+        got = orc.HB(comp, a1, a2, s1, s2, L2)
+        assert abs(got - ref) <= 1e-13 * abs(ref), (w, comp, a1, a2, got, ref)
