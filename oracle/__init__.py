@@ -36,6 +36,9 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.oracle_K.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_rhs.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
                                  dp, dp, dp, dp]
         L.oracle_rhs_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
@@ -110,6 +113,15 @@ def rk4(M, nu, lambda0, t0, dt, nsteps, x, mom):
     if rc != 0:
         raise ValueError("oracle_rk4: invalid arguments")
     return x, mom
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().oracle_max_threads())
 
 
 def H_origin(comp, a1, a2, Lam2):

@@ -34,6 +34,7 @@
  * Moment layout: shell-major, ord k = k1+k2 = 0..M, then k2 ascending;
  * index(k1,k2) = s(s+1)/2 + k2 with s = k1+k2; K = (M+1)(M+2)/2 per vortex.
  */
+#include <omp.h>
 #include <quadmath.h>
 #include <stdlib.h>
 #include <string.h>
@@ -88,6 +89,10 @@ static int idx(int k1, int k2)
 }
 
 int oracle_K(int M) { return K_of(M); }
+
+/* threads of the parallel loops (the CPU-baseline timing runs 1 and all) */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------
  * H_1, H_2: derivatives at b = 0 of the two components of the velocity of a

@@ -16,6 +16,9 @@ extern "C" {
 #endif
 
 int oracle_K(int M);
+/* threads used by the parallel loops (no effect on results) */
+void oracle_set_threads(int n);
+int oracle_max_threads(void);
 /* dM/dt and dx/dt at time t (eq:Final_CrossCoef, eq:xjdot_Final; for N = 1,
  * eq:moment_evolutionFinish).  lambda_j(t)^2 = lambda0_j^2 + 4 nu t. */
 int oracle_rhs(int N, int M, double nu, const double* lambda0, double t, const double* x,

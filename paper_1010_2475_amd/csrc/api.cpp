@@ -271,7 +271,7 @@ Workspace::~Workspace()
 namespace {
 struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
-        sselflo, spair, spad, ystate[2], accd, gpartd, gpart, clock, total;
+        sselflo, spair, ppart, spad, ystate[2], accd, gpartd, gpart, clock, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 {
@@ -304,6 +304,8 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     L.sself = add(sizeof(double) * (size_t)N_ * KG);
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
+    // partial tables of the few-vortex pair kernel (interacting vortices of the unrolled orders)
+    L.ppart = add((!solo && N_ > 1 && M_ <= kMaxPairOrder) ? sizeof(double) * (size_t)kPairSplitMaxPartials * KG : 0);
     L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
         const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
@@ -345,6 +347,7 @@ size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs*
     bufs.s_self = (double*)(b + L.sself);
     bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
     bufs.s_pair = (double*)(b + L.spair);
+    bufs.p_part = (!solo && N_ > 1 && M_ <= kMaxPairOrder) ? (double*)(b + L.ppart) : nullptr;
     bufs.s_pad = (double*)(b + L.spad);
     for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
     bufs.accD = mx ? (double*)(b + L.accd) : nullptr;

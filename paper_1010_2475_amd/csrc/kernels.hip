@@ -376,7 +376,7 @@ hipError_t launch_self(const DevTables& T, const StageBufs& B, int cur, bool dd,
 template <int M>
 hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
 
-bool pair_order_supported(int M) { return M >= 0 && M <= MMVM_MAX_ORDER; }
+bool pair_order_supported(int M) { return M >= 0 && M <= MMVM_MAX_PAIR_ORDER; }
 
 hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
@@ -397,6 +397,24 @@ hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32
 {
     if (T.M > kMaxPairOrder) return launch_pair_gen(T, B, cur, st);
     return launch_pair_shape(T, B, cur, f32, pair_shape_for(T, B, cur, f32, st), st);
+}
+
+__global__ __launch_bounds__(128) void k_pair_sum(int G, int KG, const double* __restrict__ part,
+                                                  double* __restrict__ spair)
+{
+    const int j = blockIdx.x;
+    for (int g = threadIdx.x; g < KG; g += blockDim.x) {
+        double v = 0.0;
+        for (int q = 0; q < G; ++q) v += part[((long)j * G + q) * KG + g];
+        spair[(long)j * KG + g] = v;
+    }
+}
+
+hipError_t launch_pair_sum(const StageBufs& B, int groups, int KG, hipStream_t st)
+{
+    if (!B.p_part || (long)B.N * groups > kPairSplitMaxPartials) return hipErrorInvalidValue;
+    launch_kernel(k_pair_sum, dim3(B.N), dim3(128), 0, st, groups, KG, (const double*)B.p_part, B.s_pair);
+    return hipGetLastError();
 }
 
 // The pair table joins the self table as the operand of the large-order stage

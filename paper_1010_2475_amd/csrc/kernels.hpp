@@ -55,6 +55,7 @@ struct StageBufs {
     double* s_self;        // [N][KG] self velocity-derivative table (lambda units)
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
+    double* p_part;        // [kPairSplitMaxPartials][KG] partial pair tables of split source groups (or null)
     double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
@@ -134,14 +135,35 @@ hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const Appl
 // shape: split wavefronts per target (they share its sources), tpb targets
 // per workgroup; launch_pair takes the shape the autotuner picked for
 // (order, precision, N).
+// kind 0: the unrolled kernel, one pair per lane (split, tpb as above);
+// kind 1: the few-vortex kernel, one pair per 16 lanes, a target's sources
+// split over `groups` workgroups (pair_split.hpp).
 struct PairShape {
     int split = 1, tpb = 4;
+    int kind = 0, groups = 1;
 };
 constexpr int kPairMaxThreads = 256;  // the kernel keeps up to 256 VGPRs + AGPRs per lane
+// largest N * groups of a split launch with groups > 1 (the partial tables' region)
+constexpr int kPairSplitMaxPartials = 1024;
 inline bool pair_shape_valid(PairShape s)
 {
-    return s.split >= 1 && s.tpb >= 1 && (s.split & (s.split - 1)) == 0 && 64 * s.split * s.tpb <= kPairMaxThreads;
+    if (s.kind == 1) return s.groups >= 1 && s.groups <= kPairSplitMaxPartials;
+    return s.kind == 0 && s.split >= 1 && s.tpb >= 1 && (s.split & (s.split - 1)) == 0 &&
+           64 * s.split * s.tpb <= kPairMaxThreads;
 }
+// source groups of the few-vortex kernel for N vortices: at least 16 sources
+// per group and about 512 workgroups in all
+inline int pair_split_groups(int N)
+{
+    int g = (512 + N - 1) / N;
+    const int cap = (N + 15) / 16;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    while (g > 1 && (long)N * g > kPairSplitMaxPartials) --g;
+    return g;
+}
+// s_pair[j][g] = sum over the groups of the few-vortex kernel's partial tables, in group order
+hipError_t launch_pair_sum(const StageBufs& B, int groups, int KG, hipStream_t st);
 hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
 hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
 // the autotuner's shape for this launch (times the candidates on first use of a key)
@@ -219,8 +241,9 @@ struct T0Shape {
     }
 };
 
-// the unrolled pair kernel is compiled for orders 0..kMaxPairOrder; above, the
-// runtime-order kernel (pair_gen.hip) runs, in FP64 for both precisions
+// the unrolled pair kernel is compiled for orders 0..kMaxPairOrder; above, up to
+// MMVM_MAX_PAIR_ORDER, the runtime-order kernel (pair_gen.hip) runs, in FP64 for
+// both precisions
 constexpr int kMaxPairOrder = 6;
 bool pair_order_supported(int M);
 hipError_t launch_pair_gen(const DevTables& T, const StageBufs& B, int cur, hipStream_t st);

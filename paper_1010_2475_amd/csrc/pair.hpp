@@ -6,6 +6,7 @@
 #include <utility>
 
 #include "kernels.hpp"
+#include "pair_split.hpp"
 #include "util.hpp"
 
 namespace mmvm {
@@ -61,6 +62,11 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
     constexpr int HN = P >= 2 ? P - 1 : 1;
     constexpr bool F32 = std::is_same<R, float>::value;
+    // shells n <= NF are generated and contracted in FP64: every entry g with
+    // |g| <= M + 1 (what the centre velocity and the first-moment rates read)
+    // takes terms from those shells only; the mixed kernel keeps the shells
+    // above in FP32
+    constexpr int NF = F32 ? 2 * M + 1 : P;
     constexpr double kInvPi = 0.318309886183790671537767526745;
     static_assert(P <= kPairConstShells, "edge coefficients of every shell");
 
@@ -126,35 +132,37 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
             });
         }
 
-        // 1-D Gaussian derivatives h_a(x) = d^a/dx^a exp(-x^2)
-        R h1[HN], h2[HN];
-        h1[0] = (R)e1;
-        h2[0] = (R)e2;
+        // 1-D Gaussian derivatives h_a(x) = d^a/dx^a exp(-x^2) (FP64: the FP64 shells use them)
+        double h1[HN], h2[HN];
+        h1[0] = e1;
+        h2[0] = e2;
         if constexpr (HN > 1) {
-            h1[1] = (R)(-2.0 * s1) * h1[0];
-            h2[1] = (R)(-2.0 * s2) * h2[0];
+            h1[1] = (-2.0 * s1) * h1[0];
+            h2[1] = (-2.0 * s2) * h2[0];
         }
         sfor<1, HN - 1>([&](auto a) {
-            h1[a + 1] = (R)(-2.0 * s1) * h1[a] - (R)(2 * a) * h1[a - 1];
-            h2[a + 1] = (R)(-2.0 * s2) * h2[a] - (R)(2 * a) * h2[a - 1];
+            h1[a + 1] = (-2.0 * s1) * h1[a] - (double)(2 * a) * h1[a - 1];
+            h2[a + 1] = (-2.0 * s2) * h2[a] - (double)(2 * a) * h2[a - 1];
         });
 
-        // scaled source moments
-        R am[K];
+        // scaled source moments (FP64 for the FP64 shells, R for the others)
+        double am[K];
+        R am32[F32 ? K : 1];
         {
-            const R ratio = (R)(sqrt(lp2) * ilj);
-            R rp = (R)1;
+            const double ratio = sqrt(lp2) * ilj;
+            double rp = 1.0;
             sfor<0, M + 1>([&](auto s) {
                 sfor<0, s + 1>([&](auto m2) {
                     constexpr int idx = ctri(s - m2, m2);
-                    am[idx] = aT[(long)idx * N + jp] * rp;
+                    am[idx] = (double)aT[(long)idx * N + jp] * rp;
+                    if constexpr (F32) am32[idx] = (R)am[idx];
                 });
                 rp *= ratio;
             });
         }
 
-        const R tau = (R)(lj * isc);
-        R tn = (R)1;
+        const double tau = lj * isc;
+        double tn = 1.0;
         double zr = 1.0, zi = 0.0;
         sfor<1, P + 1>([&](auto nc) {
             constexpr int n = nc;
@@ -172,23 +180,24 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
             else if constexpr (n % 4 == 1) { e0 = -hi; e1v = hr; }
             else if constexpr (n % 4 == 2) { e0 = -hr; e1v = -hi; }
             else { e0 = hi; e1v = -hr; }
-            R psi[n + 1];
-            R p0 = (R)(2.0 * e0), p1 = (R)(2.0 * e1v);
-            R prod[n >= 2 ? n - 1 : 1];
+            typedef typename std::conditional<(n <= NF), double, R>::type T;
+            T psi[n + 1];
+            T p0 = (T)(2.0 * e0), p1 = (T)(2.0 * e1v);
+            T prod[n >= 2 ? n - 1 : 1];
             if constexpr (n >= 2) {
                 sfor<0, n - 1>([&](auto cc) {
-                    prod[cc] = h1[cc] * h2[n - 2 - cc];
-                    p0 += (R)kPairKappa0[n][cc] * prod[cc];
-                    p1 += (R)kPairKappa1[n][cc] * prod[cc];
+                    prod[cc] = (T)h1[cc] * (T)h2[n - 2 - cc];
+                    p0 += (T)kPairKappa0[n][cc] * prod[cc];
+                    p1 += (T)kPairKappa1[n][cc] * prod[cc];
                 });
             }
             psi[0] = p0;
             psi[1] = p1;
             if constexpr (n >= 2) {
-                sfor<0, n - 1>([&](auto a) { psi[a + 2] = prod[a] * (R)kInvPi - psi[a]; });
+                sfor<0, n - 1>([&](auto a) { psi[a + 2] = prod[a] * (T)kInvPi - psi[a]; });
             }
             tn *= tau;
-            sfor<0, n + 1>([&](auto a) { psi[a] *= tn; });
+            sfor<0, n + 1>([&](auto a) { psi[a] *= (T)tn; });
             // Hankel contraction of this shell
             sfor<0, n + 1>([&](auto a) {
                 constexpr int m1max = a < M ? (int)a : M;
@@ -198,8 +207,8 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
                     sfor<0, m2max + 1>([&](auto m2) {
                         constexpr int g1 = a - m1, g2 = n - a - m2;
                         if constexpr (g1 + g2 >= 1 && g1 + g2 <= GM) {
-                            if constexpr (F32)
-                                acc32[ctri(g1, g2)] += am[ctri(m1, m2)] * psi[a];
+                            if constexpr (n > NF)
+                                acc32[ctri(g1, g2)] += am32[ctri(m1, m2)] * psi[a];
                             else
                                 acc[ctri(g1, g2)] = fma(am[ctri(m1, m2)], psi[a], acc[ctri(g1, g2)]);
                         }
@@ -249,6 +258,7 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     constexpr int GM = M == 0 ? 1 : 2 * M;
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
     if (!pair_shape_valid(sh)) return hipErrorInvalidValue;
+    if (sh.kind == 1) return launch_pair_split_M<M>(T, B, cur, sh.groups, st);
     const int waves = sh.split * sh.tpb;
     dim3 grid((B.N + sh.tpb - 1) / sh.tpb);
     const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;

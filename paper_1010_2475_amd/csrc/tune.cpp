@@ -92,6 +92,13 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
             s.tpb = tpb;
             if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
         }
+    // the few-vortex kernel (16 lanes per pair)
+    if (B.p_part) {
+        PairShape s;
+        s.kind = 1;
+        s.groups = pair_split_groups(B.N);
+        cand.push_back(s);
+    }
     // the tuning launches are not the caller's timed kernel
     TimingSlot* saved = timing_slot();
     timing_slot() = nullptr;
@@ -104,7 +111,7 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
             const double us = time_pair(T, B, cur, f32, s, st, e0, e1);
             if (us < 0.0) continue;
             ++best.candidates;
-            if (s.split == def.split && s.tpb == def.tpb) best.us_def = us;
+            if (s.kind == def.kind && s.split == def.split && s.tpb == def.tpb) best.us_def = us;
             if (best.us < 0.0 || us < best.us) {
                 best.us = us;
                 best.shape = s;
@@ -142,9 +149,10 @@ mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed)
         for (const auto& kv : g_pair) {
             const PairEntry& e = kv.second;
             std::snprintf(line, sizeof(line),
-                          "pair order=%d prec=%s n<=%d split=%d tpb=%d us=%.3f default_us=%.3f candidates=%d\n",
+                          "pair order=%d prec=%s n<=%d kind=%d split=%d tpb=%d groups=%d us=%.3f default_us=%.3f "
+                          "candidates=%d\n",
                           std::get<0>(kv.first), std::get<1>(kv.first) ? "mixed" : "fp64", std::get<2>(kv.first),
-                          e.shape.split, e.shape.tpb, e.us, e.us_def, e.candidates);
+                          e.shape.kind, e.shape.split, e.shape.tpb, e.shape.groups, e.us, e.us_def, e.candidates);
             out += line;
         }
     }

@@ -83,8 +83,8 @@ def test_argument_validation_without_device(mm):
     # null device pointers
     p = mm.Problem(1, 2, 0.01, dp)
     assert L.mmvm_rhs(ctypes.byref(p), 0.0, None, vp(8), vp(8), vp(8), 0, None) == -1
-    # multi-vortex problems take every order up to the maximum, and no more
-    p = mm.Problem(2, 41, 0.01, dp)
+    # multi-vortex problems take every order up to the interacting maximum, and no more
+    p = mm.Problem(2, 17, 0.01, dp)
     assert L.mmvm_rhs(ctypes.byref(p), 0.0, vp(8), vp(8), vp(8), vp(8), 0, None) == -3
     # batches: null, empty, order out of range, bad member parameters, null state
     nu = np.array([0.01, 0.02])

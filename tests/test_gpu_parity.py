@@ -606,7 +606,7 @@ def test_two_clusters_4096_sampled(env, orc, prec, tol):
     assert abs((G[:, None] * dx_g).sum(0)).max() <= tol * np.abs(G[:, None] * dx_g).sum()
 
 
-@pytest.mark.parametrize("N,M,prec", [(2, 20, 0), (2, 20, 1), (3, 16, 1), (2, 30, 0), (2, 40, 1)])
+@pytest.mark.parametrize("N,M,prec", [(2, 14, 0), (2, 16, 0), (3, 16, 1), (2, 16, 1)])
 def test_multi_vortex_high_orders_sampled_rows(env, orc, N, M, prec):
     """Interacting vortices at high orders: the runtime-order pair kernel (every
     shell up to 3M generated in LDS) feeding the matrix-core stage 2 (FP64 up to
@@ -633,3 +633,19 @@ def test_multi_vortex_high_orders_sampled_rows(env, orc, N, M, prec):
     dx_r = dxr.reshape(N, len(ks), 2)[:, 0, :]
     assert np.abs(dx_g - dx_r).max() <= tol * max(1.0, np.abs(dx_r).max())
     assert np.all(dm_g[:, 0] == 0.0)
+
+
+@pytest.mark.parametrize("M", [17, 20, 40])
+def test_multi_vortex_above_the_pair_order_is_refused(env, M):
+    """Interacting vortices above MMVM_MAX_PAIR_ORDER return MMVM_EORDER (their
+    FP64 pair contraction would not hold the error bar)."""
+    torch, mm = env
+    w = rand_workload(800 + M, 2, M)
+    X = torch.tensor(w.x, device="cuda:0")
+    Mo = torch.tensor(w.mom, device="cuda:0")
+    with pytest.raises(mm.MMVMError) as e:
+        mm.rhs(w.M, w.nu, w.lam0, 0.0, X, Mo, torch.zeros_like(X), torch.zeros_like(Mo), 0)
+    assert e.value.status == -3
+    with pytest.raises(mm.MMVMError) as e:
+        mm.step(w.M, w.nu, w.lam0, 0.0, 1e-3, 2, X, Mo, 1)
+    assert e.value.status == -3
