@@ -48,8 +48,8 @@ typedef enum {
     MMVM_EORDER = -3,     /* n < 1, order < 0, order > MMVM_MAX_ORDER, or n > 1 and order > MMVM_MAX_PAIR_ORDER */
     MMVM_EZEROCIRC = -4,  /* a vortex of a multi-vortex problem has M^j_00 == 0 (eq:mass) */
     MMVM_EDEVICE = -5,    /* HIP runtime error */
-    MMVM_ENOTFOUND = -6,  /* unknown ticket */
-    MMVM_EBUDGET = -7,    /* request footprint exceeds the server's HBM budget */
+    MMVM_ENOTFOUND = -6,  /* unknown ticket; tables of the order not prepared (mmvm_rhs_noalloc) */
+    MMVM_EBUDGET = -7,    /* footprint exceeds the server budget or the no-alloc scratch array */
     MMVM_ENONFINITE = -8  /* NaN/Inf in the state */
 } mmvm_status;
 
@@ -196,6 +196,31 @@ mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launc
  * buf == NULL just sets *needed; MMVM_EINVAL if cap is too small. */
 mmvm_status mmvm_autotune_enable(int32_t on);
 mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the right-hand side of
+ * mmvm_rhs, same arguments and results (to rounding), with every workspace
+ * region taken from one fixed array of MMVM_NOALLOC_SCRATCH_MB MiB that the
+ * library holds on each device until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine, and no host synchronisation:
+ *  - the tables of the order must already be on the device: call
+ *    mmvm_prepare(order) first (MMVM_ENOTFOUND otherwise);
+ *  - a problem whose workspace exceeds the array returns MMVM_EBUDGET (e.g.
+ *    orders <= 6 up to a few tens of thousands of vortices; one vortex at
+ *    every order);
+ *  - the pair kernel runs the launch shape the autotuner already chose for
+ *    this (order, precision, vortex count) in the process, else the default
+ *    shape: it never tunes;
+ *  - lambda0 (host) is read during the call only;
+ *  - device-side checks (zero circulation, non-finite state) are not
+ *    reported: such inputs give non-finite outputs;
+ *  - every call on a device shares that device's array: calls that overlap on
+ *    one device (other streams, other threads) race and must be serialised by
+ *    the caller. */
+#define MMVM_NOALLOC_SCRATCH_MB 64
+mmvm_status mmvm_rhs_noalloc(const mmvm_problem* prob, double t, const double* x, const double* mom,
+                             double* dx, double* dmom, mmvm_precision prec, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* mmvm_status_string(mmvm_status s);

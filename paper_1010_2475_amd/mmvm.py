@@ -51,7 +51,7 @@ _lib = None
 
 SYMBOLS = ["mmvm_coeffs", "mmvm_prepare", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
            "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
-           "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_status_string"]
+           "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_rhs_noalloc", "mmvm_status_string"]
 
 
 def lib():
@@ -66,6 +66,7 @@ def lib():
     L.mmvm_coeffs.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mmvm_prepare.argtypes = [ctypes.c_int32]
     L.mmvm_rhs.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.mmvm_rhs_noalloc.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
     L.mmvm_step.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
     L.mmvm_step_batch.argtypes = [ctypes.POINTER(Batch), ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp,
                                   ctypes.c_int, vp]
@@ -139,6 +140,16 @@ def rhs(M, nu, lambda0, t, x, mom, dx, dmom, prec=FP64, stream=None):
     _check(lib().mmvm_rhs(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
                           _dev(dx, (N, 2), "dx"), _dev(dmom, (N, K), "dmom"), int(prec), _stream(stream)),
            "mmvm_rhs")
+
+
+def rhs_noalloc(M, nu, lambda0, t, x, mom, dx, dmom, prec=FP64, stream=None):
+    """mmvm_rhs_noalloc: mmvm_rhs on the library's fixed scratch array (no allocation;
+    the order's tables must have been prepared)."""
+    p, lam = _problem(M, nu, lambda0)
+    N, K = p.n, K_of(M)
+    _check(lib().mmvm_rhs_noalloc(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
+                                  _dev(dx, (N, 2), "dx"), _dev(dmom, (N, K), "dmom"), int(prec),
+                                  _stream(stream)), "mmvm_rhs_noalloc")
 
 
 def prepare(M):
