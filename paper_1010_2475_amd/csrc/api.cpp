@@ -286,7 +286,7 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
         return o;
     };
     L.flag = add(sizeof(int) * 16);  // first: fixed offset across layouts
-    L.lam0 = add(sizeof(double) * 2 * N_);  // lambda_{j,0}^2 and nu_j
+    L.lam0 = add(sizeof(double) * 3 * N_);  // lambda_{j,0}^2, nu_j and the time offset of vortex j
     L.xs = add(sizeof(double) * 2 * N_);
     L.ys = add(sizeof(double) * (size_t)N_ * K);
     L.accx = add(sizeof(double) * 2 * N_);
@@ -305,7 +305,8 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     L.sselflo = add(need_dd ? sizeof(double) * (size_t)N_ * KG : 0);
     L.spair = add(sizeof(double) * (size_t)N_ * KG);
     // partial tables of the few-vortex pair kernel (interacting vortices of the unrolled orders)
-    L.ppart = add((!solo && N_ > 1 && M_ <= kMaxPairOrder) ? sizeof(double) * (size_t)kPairSplitMaxPartials * KG : 0);
+    const bool split = !solo && N_ > 1 && M_ <= kMaxPairOrder && pair_split_groups(N_) > 1;
+    L.ppart = add(split ? sizeof(double) * (size_t)N_ * pair_split_groups(N_) * KG : 0);
     L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
         const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
@@ -331,6 +332,7 @@ size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs*
     bufs.interact = (!solo && N_ > 1) ? 1 : 0;
     bufs.lam0sq = (const double*)(b + L.lam0);
     bufs.nuv = (const double*)(b + L.lam0) + N_;
+    bufs.toff = (const double*)(b + L.lam0) + 2 * (size_t)N_;
     bufs.xs = (double*)(b + L.xs);
     bufs.ys = (double*)(b + L.ys);
     bufs.accx = (double*)(b + L.accx);
@@ -347,7 +349,9 @@ size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs*
     bufs.s_self = (double*)(b + L.sself);
     bufs.s_self_lo = need_dd ? (double*)(b + L.sselflo) : nullptr;
     bufs.s_pair = (double*)(b + L.spair);
-    bufs.p_part = (!solo && N_ > 1 && M_ <= kMaxPairOrder) ? (double*)(b + L.ppart) : nullptr;
+    bufs.p_part = (!solo && N_ > 1 && M_ <= kMaxPairOrder && pair_split_groups(N_) > 1) ? (double*)(b + L.ppart)
+                                                                                          : nullptr;
+    bufs.pair_groups = 0;
     bufs.s_pad = (double*)(b + L.spad);
     for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
     bufs.accD = mx ? (double*)(b + L.accd) : nullptr;
@@ -398,12 +402,14 @@ mmvm_status Workspace::ensure(int N_, int M_, bool need_dd, bool solo, hipStream
     return MMVM_OK;
 }
 
-mmvm_status Workspace::set_params(const double* lambda0, const double* nu, double nu0, int N_, hipStream_t st)
+mmvm_status Workspace::set_params(const double* lambda0, const double* nu, double nu0, int N_, hipStream_t st,
+                                  const double* toff)
 {
-    std::vector<double> p(2 * (size_t)N_);
+    std::vector<double> p(3 * (size_t)N_);
     for (int j = 0; j < N_; ++j) {
         p[j] = lambda0[j] * lambda0[j];
         p[N_ + j] = nu ? nu[j] : nu0;
+        p[2 * (size_t)N_ + j] = toff ? toff[j] : 0.0;
     }
     if (p == par_cache) return MMVM_OK;
     // The device copy may be read by queued work, so the update is ordered on
@@ -481,18 +487,27 @@ mmvm_status run_stage_bufs(const DevTables& T, const StageBufs& B, mmvm_precisio
         timing_end(tk, "self", st);
         if (e != hipSuccess) return hip_status(e, "k_self launch");
     }
+    StageBufs B2 = B;  // the stage-2 kernel learns how the pair table was left
+    B2.pair_groups = 0;
     if (pair) {
+        PairShape used;
         tk = timing_begin(st);
-        e = shape ? launch_pair_shape(T, B, A.cur, f32, *shape, st) : launch_pair(T, B, A.cur, f32, st);
+        if (shape) {
+            used = *shape;
+            e = launch_pair_shape(T, B, A.cur, f32, used, st);
+        } else {
+            e = launch_pair(T, B, A.cur, f32, st, &used);
+        }
         timing_end(tk, "pair", st);
         if (e != hipSuccess) return hip_status(e, "k_pair launch");
+        if (used.kind == 1 && T.M <= kMaxPairOrder && pair_split_groups(B.N) > 1) B2.pair_groups = pair_split_groups(B.N);
         if (dd || stage2_uses_mfma(T.M, dd, false)) {
             e = launch_pair_into_stage2(T, B, dd, st);
             if (e != hipSuccess) return hip_status(e, "k_pair_into_stage2 launch");
         }
     }
     tk = timing_begin(st);
-    e = launch_stage2(T, B, A, dd, st);
+    e = launch_stage2(T, B2, A, dd, st);
     timing_end(tk, "stage2", st);
     if (e != hipSuccess) return hip_status(e, "k_stage2 launch");
     if (!stage2_needs_emit(T.M, dd, !B.interact)) return MMVM_OK;

@@ -22,7 +22,7 @@ struct Workspace {
     int N = 0, M = 0;
     StageBufs bufs{};
     int* flag_ptr = nullptr;
-    double* par_dev = nullptr;       // [2N]: lambda_{j,0}^2, then the viscosity of each vortex
+    double* par_dev = nullptr;       // [3N]: lambda_{j,0}^2, the viscosity and the time offset of each vortex
     std::vector<double> par_cache;
     hipEvent_t par_event = nullptr;    // the upload from par_cache has completed
     int latched = 0;
@@ -46,8 +46,10 @@ struct Workspace {
     // solo: the vortices do not interact (N = 1, or a batch of independent solves)
     mmvm_status ensure(int N, int M, bool need_dd, bool solo, hipStream_t st);
     static size_t bytes_for(int N, int M, bool need_dd, bool solo);
-    // lambda0 [N]; viscosity nu[N], or the scalar nu0 for every vortex when nu is null
-    mmvm_status set_params(const double* lambda0, const double* nu, double nu0, int N, hipStream_t st);
+    // lambda0 [N]; viscosity nu[N], or the scalar nu0 for every vortex when nu is null;
+    // toff [N]: each vortex's time offset (null: zero)
+    mmvm_status set_params(const double* lambda0, const double* nu, double nu0, int N, hipStream_t st,
+                           const double* toff = nullptr);
     void release();
     ~Workspace();
 };
@@ -57,7 +59,7 @@ mmvm_status device_tables(int M, const DevTables** out);
 const DevTables* find_device_tables(int M);
 // Lays out the workspace regions of one solve of N vortices at order M from
 // `base` (256-byte aligned regions; the error flag first) and binds them to
-// *bufs, *clock and *par ([2N]: lambda_{j,0}^2, then nu_j); returns the bytes
+// *bufs, *clock and *par ([3N]: lambda_{j,0}^2, nu_j, time offsets); returns the bytes
 // needed.  With base == nullptr it only returns the size.
 size_t stage_layout(char* base, int N, int M, bool need_dd, bool solo, StageBufs* bufs, DevClock** clock,
                     double** par);

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
     const long total = (long)N * K;
     for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
         int j = (int)(idx / K), k = (int)(idx - (long)j * K);
-        double l2 = lam0sq[j] + 4.0 * B.nuv[j] * t;
+        double l2 = lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(t, B.toff[j]);
         double mk = min_[idx];
         const int sk = shell_of(k);
         double a = mk * inv_lambda_pow(l2, sk);
@@ -135,7 +135,7 @@ hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const do
     if (blocks > 4096) blocks = 4096;
     bool copy = (min_ != B.ys);
     launch_kernel(k_prep, dim3(blocks), dim3(256), 0, st, B, cur, T.M, B.N, T.K, xin, min_, B.lam0sq, t, B.xs,
-                       B.ys, B.lam2[cur], B.alpha[cur], need_pair && !need_f32 ? B.alphaT[cur] : (double*)nullptr,
+                       B.ys, B.lam2[cur], B.alpha[cur], need_pair ? B.alphaT[cur] : (double*)nullptr,
                        need_pair && need_f32 ? B.alphaT32[cur] : (float*)nullptr, B.flag, copy ? 1 : 0);
     if (B.alphaD[0]) {  // zeros of the dense layouts (disjoint from what k_prep writes)
         const int LP = 16 * ((T.M + 16) / 16);
@@ -183,8 +183,9 @@ __device__ __forceinline__ void emit_moment(const StageBufs& B, const StageArgs&
         store_dense_alpha(B, nx, M, j, s - k2, k2, a);
     }
     if (S.want_pair) {
+        // FP64 always (the mixed path may run the FP64 pair kernel), FP32 for the mixed kernel
+        B.alphaT[nx][(long)k * B.N + j] = a;
         if (S.want_f32) B.alphaT32[nx][(long)k * B.N + j] = (float)a;
-        else B.alphaT[nx][(long)k * B.N + j] = a;
     }
 }
 
@@ -393,28 +394,15 @@ hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bo
     }
 }
 
-hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st)
+hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st, PairShape* used)
 {
-    if (T.M > kMaxPairOrder) return launch_pair_gen(T, B, cur, st);
-    return launch_pair_shape(T, B, cur, f32, pair_shape_for(T, B, cur, f32, st), st);
-}
-
-__global__ __launch_bounds__(128) void k_pair_sum(int G, int KG, const double* __restrict__ part,
-                                                  double* __restrict__ spair)
-{
-    const int j = blockIdx.x;
-    for (int g = threadIdx.x; g < KG; g += blockDim.x) {
-        double v = 0.0;
-        for (int q = 0; q < G; ++q) v += part[((long)j * G + q) * KG + g];
-        spair[(long)j * KG + g] = v;
+    if (T.M > kMaxPairOrder) {
+        if (used) *used = PairShape();
+        return launch_pair_gen(T, B, cur, st);
     }
-}
-
-hipError_t launch_pair_sum(const StageBufs& B, int groups, int KG, hipStream_t st)
-{
-    if (!B.p_part || (long)B.N * groups > kPairSplitMaxPartials) return hipErrorInvalidValue;
-    launch_kernel(k_pair_sum, dim3(B.N), dim3(128), 0, st, groups, KG, (const double*)B.p_part, B.s_pair);
-    return hipGetLastError();
+    const PairShape sh = pair_shape_for(T, B, cur, f32, st);
+    if (used) *used = sh;
+    return launch_pair_shape(T, B, cur, f32, sh, st);
 }
 
 // The pair table joins the self table as the operand of the large-order stage
@@ -1195,7 +1183,7 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         const double wst = (P.stage == 0 || P.stage == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
         const double cnx = P.stage < 2 ? 0.5 : 1.0;
         const bool writer = r == 0;
-        const double l0sq = B.lam0sq[j], nuj = B.nuv[j];  // issued with the operand loads
+        const double l0sq = B.lam0sq[j], nuj = B.nuv[j], tfj = B.toff[j];  // issued with the operand loads
         double2 vt2[kRowSlots];
         double pg[kRowSlots][4], pc[kRowSlots], py[kRowSlots], pa[kRowSlots];
         const long LL = (long)LP * LP;
@@ -1228,8 +1216,8 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
                 tp = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_prev), P.c_prev), P.dt));
                 tn = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_next), P.c_next), P.dt));
             }
-            const double lam2p = l0sq + 4.0 * nuj * tp;
-            const double lam2n = l0sq + 4.0 * nuj * tn;
+            const double lam2p = l0sq + 4.0 * nuj * __dadd_rn(tp, tfj);
+            const double lam2n = l0sq + 4.0 * nuj * __dadd_rn(tn, tfj);
             pw[0][tid] = pow_uint(sqrt(lam2p), tid) / lam2p;
             pw[1][tid] = pow_uint(1.0 / sqrt(lam2n), tid);
             if (writer && par == 0 && tid == 0) B.lam2[cur][j] = lam2n;
@@ -1331,7 +1319,7 @@ __global__ __launch_bounds__(1024) void k_apply_final(DevTables T, StageBufs B, 
     const int j = blockIdx.x, K = T.K;
     const int LP = 16 * ((T.M + 16) / 16);
     const long LL = (long)LP * LP;
-    const double lam2p = B.lam0sq[j] + 4.0 * B.nuv[j] * P.t_prev;
+    const double lam2p = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(P.t_prev, B.toff[j]);
     const double lamp = sqrt(lam2p);
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         const int s = shell_of(k);
@@ -1392,7 +1380,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
     double tn = S.t_next;
     if (S.clock)  // as the host evaluates t0 + (n + c) dt: separate roundings
         tn = __dadd_rn(S.clock->t0, __dmul_rn(__dadd_rn((double)(S.clock->n + S.n_rel), S.c_next), S.dt));
-    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * tn;
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(tn, B.toff[j]);
     double xd1 = 0.0, xd2 = 0.0;
     if (B.interact) centre_velocity(al, sp, K, lam, red, xd1, xd2);
     const double* gj = B.gpart + (long)j * 4 * K * 2;
@@ -1657,8 +1645,19 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
     }
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * S.t_next;
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(S.t_next, B.toff[j]);
     const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
+    __shared__ double spl[KG];
+    if (B.interact && B.pair_groups > 1) {
+        // the few-vortex pair kernel left one partial table per source group: add them in group order
+        const double* part = B.p_part + (long)j * B.pair_groups * KG;
+        for (int g = tid; g < KG; g += nt) {
+            double v = 0.0;
+            for (int q = 0; q < B.pair_groups; ++q) v += part[(long)q * KG + g];
+            spl[g] = v;
+        }
+        sp = spl;
+    }
     small_load_tables<M>(T, smem);
     __syncthreads();
     double xd1 = 0.0, xd2 = 0.0;
@@ -1683,15 +1682,16 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
 // ---------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(1024) void k_solo_rk4(DevTables T, const double* __restrict__ lam0sq,
-                                                   const double* __restrict__ nuv, double t0, double dt,
-                                                   int64_t nsteps, double* __restrict__ mom, int* __restrict__ flag)
+                                                   const double* __restrict__ nuv, const double* __restrict__ toff,
+                                                   double t0, double dt, int64_t nsteps, double* __restrict__ mom,
+                                                   int* __restrict__ flag)
 {
     typedef SmallShape<M> Sh;
     constexpr int K = Sh::K;
     static_assert(K <= 1024, "one thread per moment");
     extern __shared__ double smem[];
     const int j = blockIdx.x, tid = threadIdx.x;
-    const double l0 = lam0sq[j], nu = nuv[j];
+    const double l0 = lam0sq[j], nu = nuv[j], tf = toff[j];
     double* my = mom + (long)j * K;
     const bool owner = tid < K;
     const int sk = owner ? shell_of(tid) : 0;
@@ -1708,7 +1708,7 @@ __global__ __launch_bounds__(1024) void k_solo_rk4(DevTables T, const double* __
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int s = 0; s < 4; ++s) {
             const double ts = t0 + ((double)n + cst[s]) * dt;
-            const double lam2 = l0 + 4.0 * nu * ts;
+            const double lam2 = l0 + 4.0 * nu * __dadd_rn(ts, tf);
             if (owner) small_put_alpha<M>(smem, tid, sk, k1, k2, ys * inv_lambda_pow(lam2, sk));
             __syncthreads();
             small_stage<M>(smem, nullptr);
@@ -1754,8 +1754,9 @@ static hipError_t launch_small(const DevTables& T, const StageBufs& B, const Sta
 }
 
 template <int M>
-static hipError_t launch_solo_M(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0,
-                                double dt, int64_t nsteps, double* mom, int* flag, hipStream_t st)
+static hipError_t launch_solo_M(const DevTables& T, int nb, const double* lam0sq, const double* nuv,
+                                const double* toff, double t0, double dt, int64_t nsteps, double* mom, int* flag,
+                                hipStream_t st)
 {
     typedef SmallShape<M> Sh;
     if (T.T0N != Sh::T0N) return hipErrorInvalidValue;
@@ -1766,28 +1767,28 @@ static hipError_t launch_solo_M(const DevTables& T, int nb, const double* lam0sq
         if (ea != hipSuccess) return ea;
     }
     const int threads = Sh::K > 256 ? 1024 : kSoloThreads;
-    launch_kernel(k_solo_rk4<M>, dim3(nb), dim3(threads), shmem, st, T, lam0sq, nuv, t0, dt, nsteps, mom, flag);
+    launch_kernel(k_solo_rk4<M>, dim3(nb), dim3(threads), shmem, st, T, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag);
     return hipGetLastError();
 }
 
 bool solo_persistent(int M, bool dd) { return !dd && M >= 0 && M <= kMaxSoloOrder; }
 
-hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0, double dt,
-                           int64_t nsteps, double* mom, int* flag, hipStream_t st)
+hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, const double* toff,
+                           double t0, double dt, int64_t nsteps, double* mom, int* flag, hipStream_t st)
 {
     switch (T.M) {
-    case 0: return launch_solo_M<0>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 1: return launch_solo_M<1>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 2: return launch_solo_M<2>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 3: return launch_solo_M<3>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 4: return launch_solo_M<4>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 5: return launch_solo_M<5>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 6: return launch_solo_M<6>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 7: return launch_solo_M<7>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 8: return launch_solo_M<8>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 9: return launch_solo_M<9>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 10: return launch_solo_M<10>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
-    case 11: return launch_solo_M<11>(T, nb, lam0sq, nuv, t0, dt, nsteps, mom, flag, st);
+    case 0: return launch_solo_M<0>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 1: return launch_solo_M<1>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 2: return launch_solo_M<2>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 3: return launch_solo_M<3>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 4: return launch_solo_M<4>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 5: return launch_solo_M<5>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 6: return launch_solo_M<6>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 7: return launch_solo_M<7>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 8: return launch_solo_M<8>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 9: return launch_solo_M<9>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 10: return launch_solo_M<10>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
+    case 11: return launch_solo_M<11>(T, nb, lam0sq, nuv, toff, t0, dt, nsteps, mom, flag, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -44,6 +44,8 @@ struct StageBufs {
     int interact;          // the vortices interact (N > 1 and not a batch of independent solves)
     const double* lam0sq;  // [N] lambda_{j,0}^2
     const double* nuv;     // [N] viscosity of the solve each vortex belongs to
+    const double* toff;    // [N] time offset of each vortex: lambda_j(t) is evaluated at t + toff[j]
+                           // (zero except for a server batch of solves at different times)
     double* xs;            // [N][2] stage input positions
     double* ys;            // [N][K] stage input moments
     double* accx;          // [N][2] RK4 accumulators
@@ -55,7 +57,8 @@ struct StageBufs {
     double* s_self;        // [N][KG] self velocity-derivative table (lambda units)
     double* s_self_lo;     // [N][KG] its low part (double-double path), or null
     double* s_pair;        // [N][KG] pair velocity-derivative table
-    double* p_part;        // [kPairSplitMaxPartials][KG] partial pair tables of split source groups (or null)
+    double* p_part;        // [N][groups][KG] partial pair tables of split source groups (or null)
+    int pair_groups;       // > 1: the pair table is the sum of these partial tables (set per stage)
     double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
@@ -135,15 +138,18 @@ hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const Appl
 // shape: split wavefronts per target (they share its sources), tpb targets
 // per workgroup; launch_pair takes the shape the autotuner picked for
 // (order, precision, N).
-// kind 0: the unrolled kernel, one pair per lane (split, tpb as above);
+// kind 0: the unrolled kernel, one pair per lane (split, tpb as above; for the
+// mixed precision f64 = 1 runs its FP64 variant);
 // kind 1: the few-vortex kernel, one pair per 16 lanes, a target's sources
-// split over `groups` workgroups (pair_split.hpp).
+// split over pair_split_groups(N) workgroups whose partial tables the stage-2
+// kernel adds (pair_split.hpp); `groups` records the count at tuning time.
 struct PairShape {
     int split = 1, tpb = 4;
     int kind = 0, groups = 1;
+    int f64 = 0;
 };
 constexpr int kPairMaxThreads = 256;  // the kernel keeps up to 256 VGPRs + AGPRs per lane
-// largest N * groups of a split launch with groups > 1 (the partial tables' region)
+// largest N * groups of a split launch with groups > 1
 constexpr int kPairSplitMaxPartials = 1024;
 inline bool pair_shape_valid(PairShape s)
 {
@@ -162,9 +168,9 @@ inline int pair_split_groups(int N)
     while (g > 1 && (long)N * g > kPairSplitMaxPartials) --g;
     return g;
 }
-// s_pair[j][g] = sum over the groups of the few-vortex kernel's partial tables, in group order
-hipError_t launch_pair_sum(const StageBufs& B, int groups, int KG, hipStream_t st);
-hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
+
+hipError_t launch_pair(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st,
+                       PairShape* used = nullptr);
 hipError_t launch_pair_shape(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st);
 // the autotuner's shape for this launch (times the candidates on first use of a key)
 PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f32, hipStream_t st);
@@ -175,8 +181,8 @@ constexpr int kMaxSmallOrder = 10;
 constexpr int kMaxSoloOrder = 11;
 constexpr int kSoloThreads = 1024;
 bool solo_persistent(int M, bool dd);
-hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, double t0, double dt,
-                           int64_t nsteps, double* mom, int* flag, hipStream_t st);
+hipError_t launch_solo_rk4(const DevTables& T, int nb, const double* lam0sq, const double* nuv, const double* toff,
+                           double t0, double dt, int64_t nsteps, double* mom, int* flag, hipStream_t st);
 bool stage2_fuses_self(int M, bool dd, bool solo);
 // stage-2 contraction; at small orders also the drift and the RK4 bookkeeping
 hipError_t launch_stage2(const DevTables& T, const StageBufs& B, const StageArgs& A, bool dd,

@@ -6,7 +6,6 @@
 #include <utility>
 
 #include "kernels.hpp"
-#include "pair_split.hpp"
 #include "util.hpp"
 
 namespace mmvm {
@@ -18,6 +17,12 @@ constexpr int kSeriesTerms = 56;
 // the edge coefficients kappa_e[n][c] and hol[n] of every shell n <= 18 as
 // constants (written by gen_pair_consts.py; the same values as the host tables)
 #include "pair_consts.inc"
+
+}  // namespace mmvm
+
+#include "pair_split.hpp"  // the few-vortex variant (uses kSeriesTerms)
+
+namespace mmvm {
 
 // 1/P! as the product 1/2 * 1/3 * ... * 1/P, each factor and product rounded
 constexpr double pair_inv_factorial(int P)
@@ -258,11 +263,11 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     constexpr int GM = M == 0 ? 1 : 2 * M;
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
     if (!pair_shape_valid(sh)) return hipErrorInvalidValue;
-    if (sh.kind == 1) return launch_pair_split_M<M>(T, B, cur, sh.groups, st);
+    if (sh.kind == 1) return launch_pair_split_M<M>(T, B, cur, st);
     const int waves = sh.split * sh.tpb;
     dim3 grid((B.N + sh.tpb - 1) / sh.tpb);
     const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;
-    if (f32)
+    if (f32 && !sh.f64)
         launch_kernel((k_pair<M, float>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
                       B.alphaT32[cur], B.s_pair);
     else

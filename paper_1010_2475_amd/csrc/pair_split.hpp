@@ -17,7 +17,7 @@
 // Then the 16 pair slots are summed in slot order (deterministic).  The same
 // formulas as the unrolled kernel (pair.hpp), in FP64 for both precisions.
 // A target's sources can be split over G workgroups (grid N x G); their partial
-// tables are added in group order by k_pair_sum.
+// tables are added in group order by the stage-2 kernel that reads them.
 #pragma once
 #include "kernels.hpp"
 #include "util.hpp"
@@ -60,8 +60,13 @@ __global__ __launch_bounds__(kSplitThreads) void k_pair_split(int N, int G, cons
     __shared__ double sG[kSplitSlots][P + 1];
     __shared__ double sZr[kSplitSlots][P + 1], sZi[kSplitSlots][P + 1];
     __shared__ double sH[2][kSplitSlots][HN];
+    __shared__ double sKap[2][P + 1][P + 1];  // the edge coefficients of every shell
 
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+    for (int e = tid; e < (P + 1) * (P + 1); e += kSplitThreads) {
+        sKap[0][e / (P + 1)][e % (P + 1)] = kap0[e];
+        sKap[1][e / (P + 1)][e % (P + 1)] = kap1[e];
+    }
     const int j = blockIdx.x / G, grp = blockIdx.x - (blockIdx.x / G) * G;
     const double xj1 = xs[2 * j], xj2 = xs[2 * j + 1], lj2 = lam2[j];
     const double ilj = 1.0 / sqrt(lj2);
@@ -88,9 +93,10 @@ __global__ __launch_bounds__(kSplitThreads) void k_pair_split(int N, int G, cons
                 double ifP = 1.0;
                 for (int f = 2; f <= P; ++f) ifP *= 1.0 / (double)f;
                 double gP;
-                if (w <= (double)P) {
+                if (w <= (double)P) {  // 56 terms reach double precision for P <= 18
                     double term = ifP, sum = 0.0;
-                    for (int k = 0; k < 64 && term > 1e-18 * sum; ++k) {
+#pragma unroll
+                    for (int k = 0; k < kSeriesTerms; ++k) {
                         sum += term;
                         term *= w * (1.0 / (double)(P + k + 1));
                     }
@@ -175,8 +181,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_pair_split(int N, int G, cons
                     default: e0 = hi; e1 = -hr; break;
                     }
                     double p0 = 2.0 * e0, p1 = 2.0 * e1;
-                    const double* k0 = kap0 + n * (P + 1);
-                    const double* k1 = kap1 + n * (P + 1);
+                    const double* k0 = sKap[0][n];
+                    const double* k1 = sKap[1][n];
                     for (int cc = 0; cc <= n - 2; ++cc) {
                         const double pr = sH[0][slot][cc] * sH[1][slot][n - 2 - cc];
                         p0 = fma(k0[cc], pr, p0);
@@ -242,19 +248,19 @@ __global__ __launch_bounds__(kSplitThreads) void k_pair_split(int N, int G, cons
 }
 
 
+// the source groups are those of pair_split_groups(N) (the shape is tuned per N
+// bucket; the group count follows the exact N)
 template <int M>
-hipError_t launch_pair_split_M(const DevTables& T, const StageBufs& B, int cur, int G, hipStream_t st)
+hipError_t launch_pair_split_M(const DevTables& T, const StageBufs& B, int cur, hipStream_t st)
 {
     typedef SplitShape<M> Sh;
-    if (G < 1 || (G > 1 && (long)B.N * G > kPairSplitMaxPartials) || !T.kap0 || T.P != Sh::P)
-        return hipErrorInvalidValue;
-    double* dst = G == 1 ? B.s_pair : B.p_part;
+    const int G = pair_split_groups(B.N);
+    if (!T.kap0 || T.P != Sh::P) return hipErrorInvalidValue;
+    double* dst = G == 1 ? B.s_pair : B.p_part;  // G > 1: partial tables [N][G][KG]
     if (!dst) return hipErrorInvalidValue;
     launch_kernel((k_pair_split<M>), dim3(B.N * G), dim3(kSplitThreads), 0, st, B.N, G, B.xs, B.lam2[cur],
                   B.alpha[cur], T.kap0, T.kap1, T.hol, dst);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && G > 1) e = launch_pair_sum(B, G, Sh::KG, st);
-    return e;
+    return hipGetLastError();
 }
 
 }  // namespace mmvm

@@ -243,7 +243,8 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, in
     if (!W.bufs.interact && solo_persistent(T.M, use_dd(T.M, prec))) {
         // small orders: every solve of the batch runs all its steps in one workgroup
         void* tk = timing_begin(st);
-        hipError_t e = launch_solo_rk4(T, W.bufs.N, W.bufs.lam0sq, W.bufs.nuv, t0, dt, nsteps, mom, W.bufs.flag, st);
+        hipError_t e = launch_solo_rk4(T, W.bufs.N, W.bufs.lam0sq, W.bufs.nuv, W.bufs.toff, t0, dt, nsteps, mom,
+                                       W.bufs.flag, st);
         timing_end(tk, "solo", st);
         if (e != hipSuccess) {
             report_hip_error(e, "k_solo_rk4 launch");

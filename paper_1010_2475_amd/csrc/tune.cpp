@@ -84,20 +84,24 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
 
     // the candidates: up to four wavefronts per workgroup, a target's sources
     // split over 1, 2 or 4 of them (each keeping at least 32 sources)
+    // (for the mixed precision also the FP64 variant of the unrolled kernel: a
+    // key may run FP64 wherever that is faster)
     std::vector<PairShape> cand;
-    for (int split = 1; split <= 4; split <<= 1)
-        for (int tpb = 1; tpb <= 4; tpb <<= 1) {
-            PairShape s;
-            s.split = split;
-            s.tpb = tpb;
-            if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
-        }
-    // the few-vortex kernel (16 lanes per pair)
-    if (B.p_part) {
+    for (int f64 = 0; f64 <= (f32 ? 1 : 0); ++f64)
+        for (int split = 1; split <= 4; split <<= 1)
+            for (int tpb = 1; tpb <= 4; tpb <<= 1) {
+                PairShape s;
+                s.split = split;
+                s.tpb = tpb;
+                s.f64 = f64;
+                if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
+            }
+    // the few-vortex kernel (16 lanes per pair, FP64)
+    if (B.N >= 2) {
         PairShape s;
         s.kind = 1;
         s.groups = pair_split_groups(B.N);
-        cand.push_back(s);
+        if (s.groups == 1 || B.p_part) cand.push_back(s);
     }
     // the tuning launches are not the caller's timed kernel
     TimingSlot* saved = timing_slot();
@@ -111,7 +115,7 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
             const double us = time_pair(T, B, cur, f32, s, st, e0, e1);
             if (us < 0.0) continue;
             ++best.candidates;
-            if (s.kind == def.kind && s.split == def.split && s.tpb == def.tpb) best.us_def = us;
+            if (s.kind == def.kind && s.split == def.split && s.tpb == def.tpb && s.f64 == def.f64) best.us_def = us;
             if (best.us < 0.0 || us < best.us) {
                 best.us = us;
                 best.shape = s;
@@ -149,10 +153,11 @@ mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed)
         for (const auto& kv : g_pair) {
             const PairEntry& e = kv.second;
             std::snprintf(line, sizeof(line),
-                          "pair order=%d prec=%s n<=%d kind=%d split=%d tpb=%d groups=%d us=%.3f default_us=%.3f "
-                          "candidates=%d\n",
+                          "pair order=%d prec=%s n<=%d kind=%d split=%d tpb=%d groups=%d f64=%d us=%.3f "
+                          "default_us=%.3f candidates=%d\n",
                           std::get<0>(kv.first), std::get<1>(kv.first) ? "mixed" : "fp64", std::get<2>(kv.first),
-                          e.shape.kind, e.shape.split, e.shape.tpb, e.shape.groups, e.us, e.us_def, e.candidates);
+                          e.shape.kind, e.shape.split, e.shape.tpb, e.shape.groups, e.shape.f64, e.us, e.us_def,
+                          e.candidates);
             out += line;
         }
     }

@@ -649,3 +649,29 @@ def test_multi_vortex_above_the_pair_order_is_refused(env, M):
     with pytest.raises(mm.MMVMError) as e:
         mm.step(w.M, w.nu, w.lam0, 0.0, 1e-3, 2, X, Mo, 1)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_high_order_stepping_matches_oracle_golden(env, prec):
+    """Single vortices of orders 17, 24 and 30 stepped a few RK4 steps against
+    the oracle's end points in tests/golden/highorder_rk4.json (written by
+    make_highorder.py from the oracle alone): the matrix-core stepping path
+    (each stage finished inside the next self kernel, graph capture on the
+    first call) and, above order 24 in FP64, the double-double path.  Bars:
+    FP64 1e-12; the mixed path contracts in plain FP64, 1e-12 up to order 24
+    and 1e-9 above (cancellation grows about 1.45x per order)."""
+    import json
+    from paper_1010_2475_amd import workloads as wl
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "highorder_rk4.json")
+    with open(path) as f:
+        gold = json.load(f)
+    assert len(gold["cases"]) >= 2
+    for c in gold["cases"]:
+        w = wl.single_random(M=c["M"], Re=c["Re"], seed=c["seed"])
+        w.dt = c["dt"]
+        _, m_g = gpu_step(env, w, c["t0"], c["steps"], prec)
+        lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * (c["t0"] + c["steps"] * w.dt))
+        tol = FP64_TOL if (prec == 0 or c["M"] <= 24) else 1e-9
+        err = normwise(w.M, lam_t, np.array([c["mom"]]), m_g)
+        assert err <= tol, (c["M"], err)
+        assert m_g[0, 0] == w.mom[0, 0]
