@@ -135,6 +135,27 @@ typedef struct {
 mmvm_status mmvm_step_batch(const mmvm_batch* batch, double t0, double dt, int64_t nsteps, double* x,
                             double* mom, mmvm_precision prec, void* stream);
 
+/* Adaptive time stepping from t0 to t1 with the Dormand-Prince 5(4) pair, the
+ * integrator of the paper's runs (section "A note on implementation and
+ * performance": ode45, RelTol = AbsTol = 1e-8), on the DEVICE state x[n][2],
+ * mom[n][K] in place, physical time.  Step-size control: the RMS over the state
+ * of e / (atol + rtol max(|y|, |y_new|)), e the embedded fourth-order error
+ * estimate, must be < 1; then h *= min(10, 0.9 err^-1/5) (no growth right after
+ * a rejection), else the step is redone with h *= max(0.2, 0.9 err^-1/5); the
+ * first step is h0 and the last one ends exactly at t1.  The host reads the
+ * error norm once per step, so the call returns when the integration is done
+ * (it synchronises `stream`).  stats (optional): accepted and rejected steps,
+ * right-hand sides evaluated, the step size the controller would take next.
+ * MMVM_EINVAL for t1 < t0, rtol < 0, atol <= 0, h0 <= 0 or a step below the
+ * resolution of t; MMVM_ENONFINITE if the error norm is not finite. */
+typedef struct {
+    int64_t accepted, rejected, rhs_evals;
+    double h_next;
+} mmvm_adaptive_stats;
+mmvm_status mmvm_integrate_adaptive(const mmvm_problem* prob, double t0, double t1, double rtol, double atol,
+                                    double h0, double* x, double* mom, mmvm_precision prec, void* stream,
+                                    mmvm_adaptive_stats* stats);
+
 /* Waits for `stream` and returns (and clears) any error latched by device-side
  * checks of earlier calls on it: MMVM_EZEROCIRC or MMVM_ENONFINITE. */
 mmvm_status mmvm_sync(void* stream);
@@ -196,6 +217,30 @@ mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launc
  * buf == NULL just sets *needed; MMVM_EINVAL if cap is too small. */
 mmvm_status mmvm_autotune_enable(int32_t on);
 mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics of the section "Shear diffusion / Results".
+ *
+ * mmvm_vorticity_grid: the vorticity reconstructed from the moments,
+ *   omega(x) = sum_j sum_{|k| <= M} M^j_k phi_k(x - x^j; lambda_j(t))
+ * (eq:moment_expansion_def_tw0, Hermite functions eq:Hermitedef of eq:phi00),
+ * on the grid x = x0 + ix h, y = y0 + iy h: omega[iy][ix], iy < ny, ix < nx,
+ * row-major, a DEVICE array of nx * ny doubles owned by the caller; x, mom are
+ * the device state as for mmvm_rhs.  FP64.  Asynchronous on `stream`; the
+ * library keeps a workspace per stream (grown on demand).  MMVM_EINVAL for bad
+ * sizes or pointers, MMVM_EORDER outside 0..MMVM_MAX_ORDER. */
+mmvm_status mmvm_vorticity_grid(const mmvm_problem* prob, double t, const double* x, const double* mom, double x0,
+                                double y0, double h, int32_t nx, int32_t ny, double* omega, void* stream);
+
+/* mmvm_enstrophy_nonaxi: the non-axisymmetric enstrophy about the centre
+ * (cx, cy) (eq:nonaxi_enstrophy), E = int (omega - <omega>_theta)^2 dx over the
+ * disc of radius rmax: the vorticity at ntheta equally spaced angles (exact
+ * for the angular modes of a vortex centred at c when ntheta > 2M) on nr rings
+ * whose squared radii are the Gauss-Legendre nodes of [0, rmax^2]
+ * (int r dr = int d(r^2) / 2).  Writes E to the DEVICE double *E.
+ * Asynchronous.  nr <= 4096, ntheta <= 8192. */
+mmvm_status mmvm_enstrophy_nonaxi(const mmvm_problem* prob, double t, const double* x, const double* mom, double cx,
+                                  double cy, double rmax, int32_t nr, int32_t ntheta, double* E, void* stream);
 
 /* ---------------------------------------------------------------------------
  * For callers that cannot allocate device memory (code under graph capture,

@@ -51,6 +51,14 @@ def lib():
         L.oracle_HB.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double]
         L.oracle_HB.restype = ctypes.c_double
+        L.oracle_dopri5.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp,
+                                    ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
+        L.oracle_vorticity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double, dp, dp,
+                                       ctypes.c_int, dp, dp, dp]
+        L.oracle_enstrophy_nonaxi.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double, dp,
+                                              dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, dp]
         L.oracle_gamma_tilde.argtypes = [ctypes.c_int] * 6 + [ctypes.c_double]
         L.oracle_gamma_tilde.restype = ctypes.c_double
         L.oracle_ck.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
@@ -113,6 +121,50 @@ def rk4(M, nu, lambda0, t0, dt, nsteps, x, mom):
     if rc != 0:
         raise ValueError("oracle_rk4: invalid arguments")
     return x, mom
+
+
+def dopri5(M, nu, lambda0, t0, t1, rtol, atol, h0, x, mom):
+    """Adaptive Dormand-Prince 5(4) from t0 to t1; returns (x, mom, accepted, rejected)."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.array(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.array(mom, dtype=np.float64).reshape(N, K_of(M))
+    acc, rej = ctypes.c_long(0), ctypes.c_long(0)
+    rc = lib().oracle_dopri5(N, M, float(nu), _dp(lambda0), float(t0), float(t1), float(rtol), float(atol),
+                             float(h0), _dp(x), _dp(mom), ctypes.byref(acc), ctypes.byref(rej))
+    if rc != 0:
+        raise ValueError("oracle_dopri5: invalid arguments")
+    return x, mom, acc.value, rej.value
+
+
+def vorticity(M, nu, lambda0, t, x, mom, px, py):
+    """omega at the points (px, py) from the moments (eq:moment_expansion_def_tw0)."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.ascontiguousarray(mom, dtype=np.float64).reshape(N, K_of(M))
+    px = np.ascontiguousarray(px, dtype=np.float64).ravel()
+    py = np.ascontiguousarray(py, dtype=np.float64).ravel()
+    out = np.zeros(len(px))
+    rc = lib().oracle_vorticity(N, M, float(nu), _dp(lambda0), float(t), _dp(x), _dp(mom), len(px), _dp(px),
+                                _dp(py), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_vorticity: invalid arguments")
+    return out
+
+
+def enstrophy_nonaxi(M, nu, lambda0, t, x, mom, cx, cy, rmax, nr, ntheta):
+    """Non-axisymmetric enstrophy about (cx, cy) (eq:nonaxi_enstrophy)."""
+    lambda0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2)
+    N = x.shape[0]
+    mom = np.ascontiguousarray(mom, dtype=np.float64).reshape(N, K_of(M))
+    E = np.zeros(1)
+    rc = lib().oracle_enstrophy_nonaxi(N, M, float(nu), _dp(lambda0), float(t), _dp(x), _dp(mom), float(cx),
+                                       float(cy), float(rmax), int(nr), int(ntheta), _dp(E))
+    if rc != 0:
+        raise ValueError("oracle_enstrophy_nonaxi: invalid arguments")
+    return float(E[0])
 
 
 def set_threads(n):

@@ -34,6 +34,7 @@
  * Moment layout: shell-major, ord k = k1+k2 = 0..M, then k2 ascending;
  * index(k1,k2) = s(s+1)/2 + k2 with s = k1+k2; K = (M+1)(M+2)/2 per vortex.
  */
+#include <math.h>
 #include <omp.h>
 #include <quadmath.h>
 #include <stdlib.h>
@@ -579,4 +580,197 @@ double oracle_ck(int k1, int k2, double lam)
 {
     init_fact();
     return (double)ck(k1, k2, (R)lam);
+}
+
+/* ------------------------------------------------------------------------
+ * Vorticity reconstruction from the moments (eq:moment_expansion_def_tw0,
+ * with the Hermite functions eq:Hermitedef and eq:phi00):
+ *   omega(x) = sum_j sum_{|k| <= M} M^j_k phi_k(x - x^j; lambda_j(t)),
+ *   phi_{k1,k2} = D_{x1}^{k1} D_{x2}^{k2} phi00,  phi00 = exp(-|x|^2/lambda^2) / (pi lambda^2).
+ * The 1-D derivatives come from the explicit Hermite-polynomial sum
+ *   d^a/du^a exp(-u^2/l^2) = exp(-u^2/l^2) a! sum_{i <= a/2} (-1)^{a-i} (2u/l^2)^{a-2i} (1/l^2)^i / (i! (a-2i)!),
+ * term by term.
+ * ---------------------------------------------------------------------- */
+static R gauss_deriv(int a, R u, R l2)
+{
+    R s = 0;
+    for (int i = 0; 2 * i <= a; ++i)
+        s += sgn(a - i) * ipow(2 * u / l2, a - 2 * i) * ipow(1 / l2, i) / (fact(i) * fact(a - 2 * i));
+    return fact(a) * s * expq(-u * u / l2);
+}
+
+static R omega_at(int N, int M, const double* lambda0, double nu, double t, const double* x, const double* mom,
+                  R p1, R p2)
+{
+    const int K = K_of(M);
+    R om = 0;
+    for (int j = 0; j < N; ++j) {
+        const R l2 = (R)lambda0[j] * (R)lambda0[j] + 4 * (R)nu * (R)t;
+        const R u1 = p1 - (R)x[2 * j], u2 = p2 - (R)x[2 * j + 1];
+        for (int s = 0; s <= M; ++s)
+            for (int k2 = 0; k2 <= s; ++k2) {
+                const int k1 = s - k2;
+                const R phik = gauss_deriv(k1, u1, l2) * gauss_deriv(k2, u2, l2) / (M_PIq * l2);
+                om += (R)mom[(size_t)j * K + idx(k1, k2)] * phik;
+            }
+    }
+    return om;
+}
+
+int oracle_vorticity(int N, int M, double nu, const double* lambda0, double t, const double* x, const double* mom,
+                     int npts, const double* px, const double* py, double* out)
+{
+    if (N < 1 || M < 0 || M > 60 || nu < 0 || npts < 0) return -1;
+    for (int j = 0; j < N; ++j)
+        if (!(lambda0[j] > 0)) return -1;
+    init_fact();
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int p = 0; p < npts; ++p) out[p] = (double)omega_at(N, M, lambda0, nu, t, x, mom, (R)px[p], (R)py[p]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Non-axisymmetric enstrophy about the centre c (eq:nonaxi_enstrophy):
+ *   E = int (omega(x) - <omega>(|x - c|))^2 dx,  <omega>(r) = (1/2pi) int_0^{2pi} omega dtheta,
+ * written out in polar coordinates about c: the azimuthal mean and integral by
+ * the trapezoidal rule on ntheta angles, the radial integral int_0^rmax r (.) dr
+ * by composite Simpson on nr (even) intervals.
+ * ---------------------------------------------------------------------- */
+int oracle_enstrophy_nonaxi(int N, int M, double nu, const double* lambda0, double t, const double* x,
+                            const double* mom, double cx, double cy, double rmax, int nr, int ntheta, double* out_E)
+{
+    if (N < 1 || M < 0 || M > 60 || nu < 0 || nr < 2 || (nr & 1) || ntheta < 1 || !(rmax > 0)) return -1;
+    for (int j = 0; j < N; ++j)
+        if (!(lambda0[j] > 0)) return -1;
+    init_fact();
+    R* ring = (R*)calloc((size_t)nr + 1, sizeof(R));  /* 2pi-normalised ring integrals of (omega - mean)^2 */
+    if (!ring) return -1;
+    const R h = (R)rmax / nr;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i <= nr; ++i) {
+        const R r = h * i;
+        R* w = (R*)malloc(sizeof(R) * (size_t)ntheta);
+        R mean = 0;
+        for (int l = 0; l < ntheta; ++l) {
+            const R th = 2 * M_PIq * l / ntheta;
+            w[l] = omega_at(N, M, lambda0, nu, t, x, mom, (R)cx + r * cosq(th), (R)cy + r * sinq(th));
+            mean += w[l];
+        }
+        mean /= ntheta;
+        R sq = 0;
+        for (int l = 0; l < ntheta; ++l) sq += (w[l] - mean) * (w[l] - mean);
+        ring[i] = r * (2 * M_PIq / ntheta) * sq;
+        free(w);
+    }
+    R E = 0;
+    for (int i = 0; i <= nr; ++i) E += ring[i] * ((i == 0 || i == nr) ? 1 : ((i & 1) ? 4 : 2));
+    E *= h / 3;
+    free(ring);
+    *out_E = (double)E;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Adaptive integration with the Dormand-Prince 5(4) pair (the method of the
+ * ode45 runs in "A note on implementation and performance", RelTol = AbsTol
+ * = 1e-8 there), on the state y = (x^j, M^j) in physical time, FP64:
+ *   stages k_i = f(t + c_i h, y + h sum_j a_ij k_j), i = 1..6, y_new = y + h sum b_i k_i,
+ *   k_7 = f(t + h, y_new), error e = h sum_i (b_i - b*_i) k_i (b* the 4th-order weights);
+ *   err = RMS_n( e_n / (atol + rtol max(|y_n|, |y_new,n|)) );
+ *   accepted when err < 1: h *= min(10, 0.9 err^(-1/5)) (no growth right after a
+ *   rejection; 10 when err = 0); rejected: h *= max(0.2, 0.9 err^(-1/5)).
+ *   The last step is clipped to end exactly at t1.
+ * Tableau of Dormand & Prince (1980).
+ * ---------------------------------------------------------------------- */
+static const double kDPc[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double kDPa[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double kDPb[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+static const double kDPbs[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100,
+                                1.0 / 40};
+
+static int dp_rhs(int N, int M, double nu, const double* lambda0, double t, const double* y, double* f)
+{
+    return oracle_rhs(N, M, nu, lambda0, t, y, y + 2 * N, f, f + 2 * N);
+}
+
+int oracle_dopri5(int N, int M, double nu, const double* lambda0, double t0, double t1, double rtol, double atol,
+                  double h0, double* x, double* mom, long* out_accepted, long* out_rejected)
+{
+    if (N < 1 || M < 0 || M > 60 || !(t1 >= t0) || !(rtol >= 0) || !(atol > 0) || !(h0 > 0)) return -1;
+    const int K = K_of(M);
+    const size_t n = 2 * (size_t)N + (size_t)N * K;
+    double* y = (double*)malloc(sizeof(double) * n);
+    double* yn = (double*)malloc(sizeof(double) * n);
+    double* ys = (double*)malloc(sizeof(double) * n);
+    double* k = (double*)malloc(sizeof(double) * n * 7);
+    if (!y || !yn || !ys || !k) return -1;
+    memcpy(y, x, sizeof(double) * 2 * N);
+    memcpy(y + 2 * N, mom, sizeof(double) * N * K);
+    long acc = 0, rej = 0;
+    double t = t0, habs = h0;
+    int rc = dp_rhs(N, M, nu, lambda0, t, y, k);
+    while (rc == 0 && t < t1) {
+        int accepted = 0, rejected = 0;
+        while (!accepted) {
+            double tn = t + habs;
+            if (tn > t1) tn = t1;
+            const double h = tn - t;
+            habs = h;
+            for (int s = 1; s < 7 && rc == 0; ++s) {
+                for (size_t i = 0; i < n; ++i) {
+                    double v = 0;
+                    for (int j = 0; j < s; ++j) v += kDPa[s][j] * k[j * n + i];
+                    ys[i] = y[i] + h * v;
+                }
+                if (s == 6) memcpy(yn, ys, sizeof(double) * n);  /* the fifth-order solution */
+                rc = dp_rhs(N, M, nu, lambda0, t + kDPc[s] * h, ys, k + s * n);
+            }
+            if (rc) break;
+            double ss = 0;
+            for (size_t i = 0; i < n; ++i) {
+                double e = 0;
+                for (int j = 0; j < 7; ++j) e += (kDPb[j] - kDPbs[j]) * k[j * n + i];
+                e *= h;
+                const double ay = y[i] < 0 ? -y[i] : y[i], an = yn[i] < 0 ? -yn[i] : yn[i];
+                const double sc = atol + (ay > an ? ay : an) * rtol;
+                ss += (e / sc) * (e / sc);
+            }
+            const double err = sqrt(ss / (double)n);
+            if (err < 1) {
+                double fac = err == 0 ? 10.0 : 0.9 * pow(err, -0.2);
+                if (fac > 10.0) fac = 10.0;
+                if (rejected && fac > 1.0) fac = 1.0;
+                habs *= fac;
+                accepted = 1;
+                t = tn;
+                memcpy(y, yn, sizeof(double) * n);
+                memcpy(k, k + 6 * n, sizeof(double) * n);  /* f(t + h, y_new): the next first stage */
+                ++acc;
+            } else {
+                double fac = 0.9 * pow(err, -0.2);
+                if (fac < 0.2) fac = 0.2;
+                habs *= fac;
+                rejected = 1;
+                ++rej;
+            }
+        }
+    }
+    if (rc == 0) {
+        memcpy(x, y, sizeof(double) * 2 * N);
+        memcpy(mom, y + 2 * N, sizeof(double) * N * K);
+    }
+    if (out_accepted) *out_accepted = acc;
+    if (out_rejected) *out_rejected = rej;
+    free(y);
+    free(yn);
+    free(ys);
+    free(k);
+    return rc;
 }

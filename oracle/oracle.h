@@ -37,6 +37,19 @@ double oracle_HB(int comp, int a1, int a2, double s1, double s2, double Lam2); /
 double oracle_gamma_tilde(int k1, int k2, int l1, int l2, int m1, int m2, double lam);
 double oracle_ck(int k1, int k2, double lam);
 
+/* adaptive Dormand-Prince 5(4) integration from t0 to t1 (error norm RMS of
+ * e / (atol + rtol max(|y|, |y_new|)), safety 0.9, step factors in [0.2, 10]),
+ * first step h0, in place on x and mom; counts of accepted and rejected steps */
+int oracle_dopri5(int N, int M, double nu, const double* lambda0, double t0, double t1, double rtol, double atol,
+                  double h0, double* x, double* mom, long* out_accepted, long* out_rejected);
+/* vorticity omega(px[p], py[p]) reconstructed from the moments (eq:moment_expansion_def_tw0) */
+int oracle_vorticity(int N, int M, double nu, const double* lambda0, double t, const double* x, const double* mom,
+                     int npts, const double* px, const double* py, double* out);
+/* non-axisymmetric enstrophy about (cx, cy) (eq:nonaxi_enstrophy): trapezoid in angle
+ * (ntheta), composite Simpson in radius on [0, rmax] (nr even) */
+int oracle_enstrophy_nonaxi(int N, int M, double nu, const double* lambda0, double t, const double* x,
+                            const double* mom, double cx, double cy, double rmax, int nr, int ntheta, double* out_E);
+
 #ifdef __cplusplus
 }
 #endif

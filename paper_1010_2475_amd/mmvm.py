@@ -42,6 +42,11 @@ class Batch(ctypes.Structure):
                 ("lambda0", ctypes.POINTER(ctypes.c_double))]
 
 
+class AdaptiveStats(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("rhs_evals", ctypes.c_int64),
+                ("h_next", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("steps", ctypes.c_int64)]
@@ -51,7 +56,8 @@ _lib = None
 
 SYMBOLS = ["mmvm_coeffs", "mmvm_prepare", "mmvm_rhs", "mmvm_step", "mmvm_step_batch", "mmvm_sync", "mmvm_server_create", "mmvm_submit",
            "mmvm_poll", "mmvm_server_drain", "mmvm_server_destroy", "mmvm_timing_enable", "mmvm_timing_get",
-           "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_rhs_noalloc", "mmvm_status_string"]
+           "mmvm_autotune_enable", "mmvm_autotune_report", "mmvm_rhs_noalloc", "mmvm_vorticity_grid",
+           "mmvm_enstrophy_nonaxi", "mmvm_integrate_adaptive", "mmvm_status_string"]
 
 
 def lib():
@@ -67,6 +73,12 @@ def lib():
     L.mmvm_prepare.argtypes = [ctypes.c_int32]
     L.mmvm_rhs.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
     L.mmvm_rhs_noalloc.argtypes = [pp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int, vp]
+    L.mmvm_integrate_adaptive.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, vp, vp, ctypes.c_int, vp, ctypes.POINTER(AdaptiveStats)]
+    L.mmvm_vorticity_grid.argtypes = [pp, ctypes.c_double, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int32, ctypes.c_int32, vp, vp]
+    L.mmvm_enstrophy_nonaxi.argtypes = [pp, ctypes.c_double, vp, vp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int32, ctypes.c_int32, vp, vp]
     L.mmvm_step.argtypes = [pp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp, ctypes.c_int, vp]
     L.mmvm_step_batch.argtypes = [ctypes.POINTER(Batch), ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp, vp,
                                   ctypes.c_int, vp]
@@ -150,6 +162,36 @@ def rhs_noalloc(M, nu, lambda0, t, x, mom, dx, dmom, prec=FP64, stream=None):
     _check(lib().mmvm_rhs_noalloc(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
                                   _dev(dx, (N, 2), "dx"), _dev(dmom, (N, K), "dmom"), int(prec),
                                   _stream(stream)), "mmvm_rhs_noalloc")
+
+
+def integrate_adaptive(M, nu, lambda0, t0, t1, rtol, atol, h0, x, mom, prec=FP64, stream=None):
+    """mmvm_integrate_adaptive: Dormand-Prince 5(4) from t0 to t1 in place on the device state;
+    returns the step statistics (accepted, rejected, rhs_evals, h_next)."""
+    p, lam = _problem(M, nu, lambda0)
+    N, K = p.n, K_of(M)
+    st = AdaptiveStats()
+    _check(lib().mmvm_integrate_adaptive(ctypes.byref(p), float(t0), float(t1), float(rtol), float(atol), float(h0),
+                                         _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"), int(prec),
+                                         _stream(stream), ctypes.byref(st)), "mmvm_integrate_adaptive")
+    return {"accepted": st.accepted, "rejected": st.rejected, "rhs_evals": st.rhs_evals, "h_next": st.h_next}
+
+
+def vorticity_grid(M, nu, lambda0, t, x, mom, x0, y0, h, nx, ny, omega, stream=None):
+    """mmvm_vorticity_grid: omega[iy][ix] at (x0 + ix h, y0 + iy h) into the device tensor omega [ny, nx]."""
+    p, lam = _problem(M, nu, lambda0)
+    N, K = p.n, K_of(M)
+    _check(lib().mmvm_vorticity_grid(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
+                                     float(x0), float(y0), float(h), int(nx), int(ny),
+                                     _dev(omega, (ny, nx), "omega"), _stream(stream)), "mmvm_vorticity_grid")
+
+
+def enstrophy_nonaxi(M, nu, lambda0, t, x, mom, cx, cy, rmax, nr, ntheta, E, stream=None):
+    """mmvm_enstrophy_nonaxi: the non-axisymmetric enstrophy about (cx, cy) into the device tensor E [1]."""
+    p, lam = _problem(M, nu, lambda0)
+    N, K = p.n, K_of(M)
+    _check(lib().mmvm_enstrophy_nonaxi(ctypes.byref(p), float(t), _dev(x, (N, 2), "x"), _dev(mom, (N, K), "mom"),
+                                       float(cx), float(cy), float(rmax), int(nr), int(ntheta), _dev(E, (1,), "E"),
+                                       _stream(stream)), "mmvm_enstrophy_nonaxi")
 
 
 def prepare(M):

@@ -478,3 +478,126 @@ def test_HB_orders_23_and_35_match_mpmath(orc, w):
         ref = float(mp.diff(_V00(comp, L2), (mp.mpf(s1), mp.mpf(s2)), (a1, a2)))
         got = orc.HB(comp, a1, a2, s1, s2, L2)
         assert abs(got - ref) <= 1e-13 * abs(ref), (w, comp, a1, a2, got, ref)
+
+
+# ---------------------------------------------------------------------------
+# Vorticity reconstruction (eq:moment_expansion_def, eq:Hermitedef): the
+# Hermite functions against sympy's derivatives of phi00, and reconstruction
+# followed by the paper's projection (eq:coefficient, with H_{n1,n2}(z;lambda)
+# = lambda^{-|n|} H_{n1}(z1/lambda) H_{n2}(z2/lambda) from the generating
+# function eq:Hermitepoly) giving back the moments.
+# ---------------------------------------------------------------------------
+def test_vorticity_hermite_functions_match_sympy(orc):
+    x1, x2 = sp.symbols("x1 x2")
+    lam = sp.Rational(13, 10)
+    phi00 = sp.exp(-(x1 ** 2 + x2 ** 2) / lam ** 2) / (sp.pi * lam ** 2)
+    pts = [(0.3, -0.7), (1.9, 0.4), (-2.2, -1.1)]
+    for (k1, k2) in [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (3, 2), (0, 5), (4, 3)]:
+        f = sp.lambdify((x1, x2), sp.diff(phi00, x1, k1, x2, k2), "mpmath")
+        M = k1 + k2
+        mom = np.zeros((1, wl.K_of(M)))
+        mom[0, wl.index(k1, k2)] = 1.0
+        got = orc.vorticity(M, 0.0, [1.3], 0.0, [[0.0, 0.0]], mom, [p[0] for p in pts], [p[1] for p in pts])
+        for i, (a, b) in enumerate(pts):
+            ref = float(f(a, b))
+            assert abs(got[i] - ref) <= 1e-14 * max(1.0, abs(ref)), (k1, k2, got[i], ref)
+
+
+def test_vorticity_projection_recovers_moments(orc):
+    from numpy.polynomial.hermite import hermgauss, hermval
+    rng = np.random.default_rng(41)
+    M, lam0, nu, t = 7, 1.4, 0.01, 0.3
+    lam = math.sqrt(lam0 ** 2 + 4 * nu * t)
+    K = wl.K_of(M)
+    mom = rng.normal(0, 0.3, (1, K))
+    xc = np.array([[0.4, -0.2]])
+    y, wq = hermgauss(24)  # int f(y) exp(-y^2) dy, exact for polynomial f of degree <= 47
+    Y1, Y2 = np.meshgrid(y, y, indexing="ij")
+    W = np.outer(wq, wq)
+    om = orc.vorticity(M, nu, [lam0], t, xc, mom, (xc[0, 0] + lam * Y1).ravel(), (xc[0, 1] + lam * Y2).ravel())
+    # omega exp(+|y|^2) is a polynomial: divide the Gaussian out, integrate against H_k
+    core = (om.reshape(Y1.shape) * np.exp(Y1 ** 2 + Y2 ** 2))
+    for (k1, k2) in wl.multi_indices(M):
+        c1 = np.zeros(k1 + 1); c1[k1] = 1.0
+        c2 = np.zeros(k2 + 1); c2[k2] = 1.0
+        Hk = lam ** (-(k1 + k2)) * hermval(Y1, c1) * hermval(Y2, c2)
+        integral = lam ** 2 * np.sum(W * Hk * core)  # dz = lam^2 dy
+        s = k1 + k2
+        proj = (-1) ** s * lam ** (2 * s) / (2 ** s * math.factorial(k1) * math.factorial(k2)) * integral
+        assert abs(proj - mom[0, wl.index(k1, k2)]) <= 1e-12 * max(1.0, np.abs(mom).max()), (k1, k2)
+
+
+# ---------------------------------------------------------------------------
+# Non-axisymmetric enstrophy (eq:nonaxi_enstrophy).  For the quadrupole
+# initial condition eq:IC_sd, omega = phi00 + 4 delta (phi20 - phi02) and
+# phi20 - phi02 = 4 r^2 cos(2 theta) phi00 / lambda^4 is a pure second angular
+# mode, so E = 16 delta^2 int (phi20 - phi02)^2 = 32 delta^2 / (pi lambda^6).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("delta,lam0", [(0.1, 2.0), (0.03, 1.3)])
+def test_enstrophy_quadrupole_closed_form(orc, delta, lam0):
+    w = wl.single_quadrupole(M=4, delta=delta)
+    w.lam0[:] = lam0
+    E = orc.enstrophy_nonaxi(w.M, 0.0, w.lam0, 0.0, w.x, w.mom, 0.0, 0.0, 7.0 * lam0, 400, 16)
+    ref = 32 * delta ** 2 / (math.pi * lam0 ** 6)
+    assert abs(E - ref) <= 1e-10 * ref, (E, ref)
+    # the same perturbation rotated by 45 degrees (M11 = 8 delta) has the same E
+    mom = np.zeros_like(w.mom)
+    mom[0, 0] = 1.0
+    mom[0, wl.index(1, 1)] = 8 * delta
+    E45 = orc.enstrophy_nonaxi(w.M, 0.0, w.lam0, 0.0, w.x, mom, 0.0, 0.0, 7.0 * lam0, 400, 16)
+    assert abs(E45 - ref) <= 1e-10 * ref
+
+
+def test_enstrophy_axisymmetric_is_zero(orc):
+    # radial shells: the Laplacian powers of phi00 (moments (2p, 2q) with binomial weights)
+    M = 6
+    mom = np.zeros((1, wl.K_of(M)))
+    mom[0, 0] = 1.0
+    for p_ in range(0, 4):
+        for q_ in range(0, 4 - p_):
+            if p_ + q_ >= 1:
+                mom[0, wl.index(2 * p_, 2 * q_)] = 0.3 ** (p_ + q_) / (math.factorial(p_) * math.factorial(q_))
+    E = orc.enstrophy_nonaxi(M, 0.0, [1.1], 0.0, [[0.0, 0.0]], mom, 0.0, 0.0, 8.0, 200, 24)
+    assert abs(E) <= 1e-26
+
+
+# ---------------------------------------------------------------------------
+# Adaptive Dormand-Prince 5(4) (the paper's ode45 runs): against SciPy's RK45
+# (the same pair and step-size controller) driving the oracle's right-hand
+# side, same first step: the same accepted and rejected steps and the same end
+# state to rounding; and at tight tolerances the classic RK4 solution with a
+# fine fixed step.
+# ---------------------------------------------------------------------------
+def test_dopri5_matches_scipy_rk45(orc):
+    from scipy.integrate import solve_ivp
+    rng = np.random.default_rng(51)
+    N, M = 2, 2
+    x, mom, lam0 = _rand_state(rng, N, M, amp=0.05, spread=0.6)
+    nu, t1, h0 = 2e-3, 0.6, 2e-2
+    K = wl.K_of(M)
+
+    def f(t, y):
+        dx, dm = orc.rhs(M, nu, lam0, t, y[:2 * N].reshape(N, 2), y[2 * N:].reshape(N, K))
+        return np.concatenate([dx.ravel(), dm.ravel()])
+
+    for tol in (1e-6, 1e-9):
+        y0 = np.concatenate([x.ravel(), mom.ravel()])
+        sol = solve_ivp(f, (0.0, t1), y0, method="RK45", rtol=tol, atol=tol, first_step=h0)
+        assert sol.success
+        xo, mo, acc, rej = orc.dopri5(M, nu, lam0, 0.0, t1, tol, tol, h0, x, mom)
+        assert acc == len(sol.t) - 1
+        assert rej == (sol.nfev - 1) // 6 - acc
+        got = np.concatenate([xo.ravel(), mo.ravel()])
+        assert np.abs(got - sol.y[:, -1]).max() <= 1e-13 * max(1.0, np.abs(sol.y[:, -1]).max())
+
+
+def test_dopri5_converges_to_the_solution(orc):
+    rng = np.random.default_rng(52)
+    N, M = 3, 3
+    x, mom, lam0 = _rand_state(rng, N, M, amp=0.05, spread=0.8)
+    nu = 1e-3
+    xo, mo, acc, rej = orc.dopri5(M, nu, lam0, 0.0, 0.4, 1e-11, 1e-11, 1e-3, x, mom)
+    xr, mr = orc.rk4(M, nu, lam0, 0.0, 2e-4, 2000, x, mom)
+    assert np.abs(mo - mr).max() <= 1e-9 * np.abs(mr).max()
+    assert np.abs(xo - xr).max() <= 1e-9
+    assert np.array_equal(mo[:, 0], mom[:, 0])  # circulation exactly conserved
