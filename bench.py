@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_FP64 = 78.6e12  # MI355X dense FP64, matrix cores and vector ALUs alike
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector (the published figure; packed FP32 instructions are not used here)
 ORDER = 40
 RES = (1e2, 1e3, 1e4)
@@ -262,7 +263,7 @@ def kernel_times(mm, torch, w, prec, steps=4):
         mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, steps, X, Mo, prec)
         mm.sync()
         out = {}
-        for k in ("prep", "self", "pair", "stage2", "emit", "apply", "solo"):
+        for k in ("prep", "self", "pair", "pair_far", "stage2", "emit", "apply", "solo"):
             ms, n = mm.timing_get(k)
             if n:
                 out[k] = {"avg_ms": ms / n, "launches": n}
@@ -305,6 +306,268 @@ def other_configs(mm, torch, wl, orc):
     return out
 
 
+
+# the paper's tab:error (section "Numerical convergence"), quoted as context
+PAPER_TAB_ERROR = {1: (0.0125, 0.0034, 0.0113, 0.0028), 2: (0.0248, 0.0067, 0.0225, 0.0058),
+                   4: (0.0488, 0.0138, 0.0443, 0.0123), 8: (0.0943, 0.0309, 0.0848, 0.0309),
+                   16: (0.1742, 0.0821, 0.1532, 0.0956)}
+
+
+def tripole_leg(mm, torch, wl, times=(1, 2, 4, 8, 16), n=256, half=4.0):
+    """The coarse-grid tripole (section "Tripole Relaxation"): the 6 x 6 grid
+    at orders 0 and 2 against the order-24 single particle, relative L2 and
+    Linf errors of the vorticity on an n x n grid over [-half, half]^2 (as in
+    tab:error).  FP64, RK4 dt 1e-3; each run stepped to the listed times and
+    reconstructed there with mmvm_vorticity_grid."""
+    dev = torch.device("cuda:0")
+    h = 2.0 * half / (n - 1)
+    runs = (("ref", wl.tripole_reference()), (0, wl.tripole_coarse(M=0)), (2, wl.tripole_coarse(M=2)))
+    fields, wall = {}, {}
+    for key, w in runs:
+        print("  tripole %s: order %d, N %d, to t=%g" % (key, w.M, w.N, times[-1]), file=sys.stderr, flush=True)
+        X = torch.tensor(w.x, device=dev)
+        Mo = torch.tensor(w.mom, device=dev)
+        om = torch.empty((n, n), dtype=torch.float64, device=dev)
+        done, out = 0, []
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for T in times:
+            k = int(round(T / w.dt)) - done
+            mm.step(w.M, w.nu, w.lam0, done * w.dt, w.dt, k, X, Mo, mm.FP64)
+            done += k
+            mm.vorticity_grid(w.M, w.nu, w.lam0, done * w.dt, X, Mo, -half, -half, h, n, n, om)
+            out.append(om.cpu().numpy())
+        wall[key] = time.perf_counter() - t_a
+        fields[key] = out
+    rows = []
+    for i, T in enumerate(times):
+        ref = fields["ref"][i]
+        r = {"t": T}
+        for M in (0, 2):
+            d = fields[M][i] - ref
+            r["e%d_L2" % M] = float(np.sqrt((d ** 2).sum() / (ref ** 2).sum()))
+            r["e%d_Linf" % M] = float(np.abs(d).max() / np.abs(ref).max())
+        r["ratio_L2"] = r["e0_L2"] / r["e2_L2"]
+        if T in PAPER_TAB_ERROR:
+            r["paper"] = dict(zip(("e0_L2", "e2_L2", "e0_Linf", "e2_Linf"), PAPER_TAB_ERROR[T]))
+        rows.append(r)
+    return {"grid": "%d x %d over [-%g, %g]^2" % (n, n, half, half), "errors": rows,
+            "wall_s": {str(k): v for k, v in wall.items()},
+            "workload": "omega_0 = phi00 + 4 delta (phi20 - phi02), lambda0 = 1, delta = 0.25, Re 1000; coarse: "
+                        "6 x 6 vortices on [-1, 1]^2 of core lambda0, circulation omega_0(x_j) times the node "
+                        "area; reference: that blurred field as one particle of order 24 (the moments of the 36 "
+                        "Gaussians about the centre)"}
+
+
+def shear_leg(mm, torch, wl, Res=(500, 800, 1000, 1500, 2000, 3000, 4000), M=24, delta=0.1, t_end=200.0,
+              dt_out=1.0):
+    """Shear diffusion (section "Shear diffusion / Results"): the perturbed
+    Lamb-Oseen vortex eq:IC_sd (delta 0.1, lambda0 2) at order 24 for the
+    paper's Reynolds numbers, stepped as one batch, with the non-axisymmetric
+    enstrophy E(t) every dt_out.  The collapse of the early decay on t/Re^{1/3}
+    is reported as the spread (max / min over Re) of the times at which E/E(0)
+    first falls below 1/2 and 1/10, scaled by Re^{1/3} and by Re."""
+    dev = torch.device("cuda:0")
+    works = [wl.single_quadrupole(M=M, delta=delta, Re=Re) for Re in Res]
+    dt = works[0].dt
+    nu = [w.nu for w in works]
+    lam = [float(w.lam0[0]) for w in works]
+    X = torch.tensor(np.concatenate([w.x for w in works]), device=dev)
+    Mo = torch.tensor(np.concatenate([w.mom for w in works]), device=dev)
+    E = torch.zeros((len(works), 1), dtype=torch.float64, device=dev)
+    nout = int(round(t_end / dt_out))
+    kout = int(round(dt_out / dt))
+    series = np.zeros((nout + 1, len(works)))
+    t_enst = 0.0
+
+    def enstrophy(step):
+        t = step * dt
+        for i, w in enumerate(works):
+            lt = math.sqrt(lam[i] ** 2 + 4.0 * nu[i] * t)
+            mm.enstrophy_nonaxi(M, nu[i], lam[i], t, X[i:i + 1], Mo[i:i + 1], 0.0, 0.0, 10.0 * lt, 512, 128, E[i])
+        return E[:, 0].cpu().numpy()
+
+    print("  shear diffusion: %d solves of order %d to t=%g" % (len(works), M, t_end), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    series[0] = enstrophy(0)
+    for o in range(1, nout + 1):
+        mm.step_batch(M, nu, lam, (o - 1) * kout * dt, dt, kout, X, Mo, mm.MIXED)
+        te = time.perf_counter()
+        series[o] = enstrophy(o * kout)
+        t_enst += time.perf_counter() - te
+    wall = time.perf_counter() - t_a
+    ts = dt_out * np.arange(nout + 1)
+    rel = series / series[0]
+
+    def first_below(col, f):
+        idx = np.nonzero(col <= f)[0]
+        if len(idx) == 0:
+            return None
+        i = idx[0]
+        # log-linear interpolation between the bracketing outputs
+        a, b = math.log(col[i - 1]), math.log(col[i])
+        return float(ts[i - 1] + (math.log(f) - a) / (b - a) * dt_out)
+
+    coll = {}
+    for f in (0.5, 0.1):
+        tf = [first_below(rel[:, i], f) for i in range(len(works))]
+        if any(v is None for v in tf):
+            coll["E/E0=%g" % f] = {"t": tf}
+            continue
+        s13 = [t / Re ** (1.0 / 3.0) for t, Re in zip(tf, Res)]
+        s1 = [t / Re for t, Re in zip(tf, Res)]
+        coll["E/E0=%g" % f] = {"t": tf, "t_over_Re13": s13, "t_over_Re": s1,
+                               "spread_Re13": max(s13) / min(s13), "spread_Re": max(s1) / min(s1)}
+    keep = list(range(0, nout + 1, max(1, nout // 50)))
+    return {"Re": list(Res), "order": M, "delta": delta, "t_end": t_end, "E0": series[0].tolist(),
+            "E_over_E0": {"t": ts[keep].tolist(), "by_Re": {str(Re): rel[keep, i].tolist()
+                                                           for i, Re in enumerate(Res)}},
+            "collapse": coll, "wall_s": wall, "enstrophy_wall_s": t_enst,
+            "quadrature": "512 Gauss-Legendre nodes in r^2 on [0, (10 lambda(t))^2], 128 angles"}
+
+
+def adaptive_leg(mm, torch, wl):
+    """The runs of the paper's implementation note, with the adaptive
+    Dormand-Prince 5(4) integrator at RelTol = AbsTol = 1e-8 (as its ode45):
+    eq:IC_sd (delta 0.1, lambda0 2) at Re 1000 from t = 0 to 2000 at orders 2,
+    18 and 22, and the 6 x 6 coarse tripole at order 2 from t = 0 to 50 (the
+    last also against fixed-step RK4 at dt 1e-3)."""
+    dev = torch.device("cuda:0")
+    cases = [("IC_sd_order2_t2000", wl.single_quadrupole(M=2, delta=0.1, Re=1000.0), 2000.0, "< 1 s"),
+             ("IC_sd_order18_t2000", wl.single_quadrupole(M=18, delta=0.1, Re=1000.0), 2000.0, "3.35 min"),
+             ("IC_sd_order22_t2000", wl.single_quadrupole(M=22, delta=0.1, Re=1000.0), 2000.0, "10.65 min"),
+             ("tripole_coarse_order2_t50", wl.tripole_coarse(M=2), 50.0, "about 6 min")]
+    out = {}
+    for name, w, T, paper in cases:
+        print("  adaptive %s" % name, file=sys.stderr, flush=True)
+        X = torch.tensor(w.x, device=dev)
+        Mo = torch.tensor(w.mom, device=dev)
+        mm.prepare(w.M)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        st = mm.integrate_adaptive(w.M, w.nu, w.lam0, 0.0, T, 1e-8, 1e-8, 1e-3, X, Mo, mm.FP64)
+        mm.sync()
+        secs = time.perf_counter() - t_a
+        r = dict(st)
+        r.update({"wall_s": secs, "t_end": T, "N": w.N, "M": w.M, "paper_ode45_wall": paper})
+        if w.N > 1:
+            X2 = torch.tensor(w.x, device=dev)
+            M2 = torch.tensor(w.mom, device=dev)
+            mm.step(w.M, w.nu, w.lam0, 0.0, 1e-3, int(round(T / 1e-3)), X2, M2, mm.FP64)
+            mm.sync()
+            a, b = Mo.cpu().numpy(), M2.cpu().numpy()
+            r["max_abs_diff_vs_rk4_dt1e-3"] = {"mom": float(np.abs(a - b).max()),
+                                               "x": float(np.abs(X.cpu().numpy() - X2.cpu().numpy()).max())}
+        out[name] = r
+    return out
+
+
+def recon_leg(mm, torch, w, X, Mo, t, n=2048, reps=5):
+    """Reconstruction of the order-40 state on an n x n grid (mmvm_vorticity_grid)
+    and its non-axisymmetric enstrophy: per-launch durations with HIP events,
+    against the grid write (HBM) and the FP64 product (2 (M+1) flops per point)."""
+    dev = torch.device("cuda:0")
+    om = torch.empty((n, n), dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    lam_t = math.sqrt(float(w.lam0[0]) ** 2 + 4.0 * w.nu * t)
+    half = 8.0 * lam_t
+    h = 2.0 * half / (n - 1)
+    mm.vorticity_grid(w.M, w.nu, w.lam0, t, X, Mo, -half, -half, h, n, n, om)  # workspace, first launch
+    mm.sync()
+    mm.timing_enable(True)
+    try:
+        for _ in range(reps):
+            mm.vorticity_grid(w.M, w.nu, w.lam0, t, X, Mo, -half, -half, h, n, n, om)
+            mm.enstrophy_nonaxi(w.M, w.nu, w.lam0, t, X, Mo, 0.0, 0.0, 10.0 * lam_t, 512, 128, E)
+        mm.sync()
+        rec_ms, rec_n = mm.timing_get("recon")
+        ens_ms, ens_n = mm.timing_get("enstrophy")
+    finally:
+        mm.timing_enable(False)
+    avg = rec_ms / max(rec_n, 1)
+    M1 = w.M + 1
+    write_b = 8.0 * n * n
+    table_b = 8.0 * M1 * 2 * n
+    flops = 2.0 * M1 * n * n
+    ach_bw = (write_b + table_b) / (avg * 1e-3)
+    return {"grid": "%d x %d" % (n, n), "order": w.M, "avg_launch_ms": avg, "launches": rec_n,
+            "roofline": {"kernel": "k_recon_grid", "bound": "hbm", "achieved": ach_bw / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": ach_bw / PEAK_HBM, "bytes_per_launch": write_b + table_b,
+                         "fp64_tflops": flops / (avg * 1e-3) / 1e12,
+                         "fp64_frac": flops / (avg * 1e-3) / PEAK_FP64},
+            "enstrophy_avg_launch_ms": ens_ms / max(ens_n, 1),
+            "enstrophy_quadrature": "512 x 128 nodes, %d vorticity evaluations per launch" % (512 * 128)}
+
+
+def dilute_leg(mm, torch, wl, orc):
+    """The dilute field (N 4096, order 4, mean spacing 2: most source chunks
+    in a target's far field), both precisions: rate, kernel durations, the
+    launch shape the tuner chose (far=1: the far chunks go to the multipole
+    kernel) and the error against the oracle on sampled rows."""
+    w = wl.dilute_multi()
+    r = {"N": w.N, "M": w.M, "steps": w.steps}
+    for pname, prec in (("mixed", mm.MIXED), ("fp64", mm.FP64)):
+        print("  dilute_multi %s: %d steps" % (pname, w.steps), file=sys.stderr, flush=True)
+        rate, ms, x, mom, t_end = run_workload(mm, torch, w, w.steps, prec)
+        e = {"moment_updates_per_s": rate, "ms_per_step": ms}
+        if orc is not None:
+            e["err_vs_oracle"] = rhs_error(mm, torch, orc, wl, w, x, mom, t_end, prec, [0, w.N // 2, w.N - 1],
+                                           list(range(w.K)))
+        kt = kernel_times(mm, torch, w, prec)
+        e["kernels_ms_per_launch"] = {k: v["avg_ms"] for k, v in kt.items()}
+        r[pname] = e
+    r["tuned_shapes"] = [ln for ln in mm.autotune_report().splitlines() if "order=4 " in ln]
+    return r
+
+
+STUDIES = ("dilute_far_field", "tripole", "shear_diffusion", "adaptive", "reconstruction")
+
+
+def run_studies(mm, torch, wl, orc, recon_state, which=STUDIES):
+    out = {}
+    for name in which:
+        print("study %s" % name, file=sys.stderr, flush=True)
+        t_a = time.perf_counter()
+        if name == "dilute_far_field":
+            r = dilute_leg(mm, torch, wl, orc)
+        elif name == "tripole":
+            r = tripole_leg(mm, torch, wl)
+        elif name == "shear_diffusion":
+            r = shear_leg(mm, torch, wl)
+        elif name == "adaptive":
+            r = adaptive_leg(mm, torch, wl)
+        else:
+            r = recon_leg(mm, torch, *recon_state)
+        r["leg_wall_s"] = time.perf_counter() - t_a
+        out[name] = r
+    return out
+
+
+def study_leg(name):
+    """One study alone (the reconstruction on the order-40 headline state
+    after 200 steps), as one JSON line."""
+    import torch
+    from paper_1010_2475_amd import mmvm as mm
+    from paper_1010_2475_amd import workloads as wl
+    mm.lib()
+    orc = None
+    if name == "dilute_far_field":
+        import oracle
+        oracle.build()
+        orc = oracle
+    state = None
+    if name == "reconstruction":
+        w = wl.single_random(M=ORDER, Re=RES[1])
+        dev = torch.device("cuda:0")
+        X = torch.tensor(w.x, device=dev)
+        Mo = torch.tensor(w.mom, device=dev)
+        mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, 200, X, Mo, mm.MIXED)
+        mm.sync()
+        state = (w, X, Mo, 200 * w.dt)
+    print(json.dumps(run_studies(mm, torch, wl, orc, state, (name,))))
+
+
 def cpu_info():
     model = None
     try:
@@ -345,7 +608,7 @@ def cpu_baseline(orc, wl, w):
             "one_thread": res["1_thread"], "cpu_model": model, "nproc": ncpu, "cpus_available": avail}
 
 
-ONLY = {"single_quadrupole": "single_quadrupole", "single_random": "single_random",
+ONLY = {"single_quadrupole": "single_quadrupole", "single_random": "single_random", "dilute_multi": "dilute_multi",
         "random_multi": "random_multi", "two_clusters": "two_clusters"}
 
 
@@ -398,9 +661,17 @@ def main():
                     help="time one workload alone (both precisions unless --precision) and print its line; for "
                          "profiling one path under rocprofv3")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default=None)
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the paper's studies (dilute far field, tripole errors, shear diffusion, adaptive "
+                         "runs, reconstruction)")
+    ap.add_argument("--study", choices=sorted(STUDIES), default=None,
+                    help="run one of the paper's studies alone and print its line")
     args = ap.parse_args()
     if args.only:
         only_leg(args)
+        return
+    if args.study:
+        study_leg(args.study)
         return
     if args.copy_calibration:
         import torch
@@ -508,6 +779,14 @@ def main():
     if not args.no_configs:
         print("timing the other workloads", file=sys.stderr, flush=True)
         out["other_configs"] = other_configs(mm, torch, wl, None if args.no_error else orc)
+
+    if not args.no_studies:
+        X0, M0 = res["mixed"]["state"]
+        dev = torch.device("cuda:0")
+        t_end = (args.warmup + args.steps) * works[0].dt
+        out["studies"] = run_studies(mm, torch, wl, None if args.no_error else orc,
+                                     (works[0], torch.tensor(X0[:1], device=dev), torch.tensor(M0[:1], device=dev),
+                                      t_end))
 
     if args.serve_requests > 0:
         print("serving %d requests" % args.serve_requests, file=sys.stderr, flush=True)

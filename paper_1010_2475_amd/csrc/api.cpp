@@ -271,7 +271,7 @@ Workspace::~Workspace()
 namespace {
 struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
-        sselflo, spair, ppart, spad, ystate[2], accd, gpartd, gpart, clock, total;
+        sselflo, spair, ppart, fmask, spad, ystate[2], accd, gpartd, gpart, clock, total;
 };
 Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 {
@@ -307,6 +307,9 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     // partial tables of the few-vortex pair kernel (interacting vortices of the unrolled orders)
     const bool split = !solo && N_ > 1 && M_ <= kMaxPairOrder && pair_split_groups(N_) > 1;
     L.ppart = add(split ? sizeof(double) * (size_t)N_ * pair_split_groups(N_) * KG : 0);
+    // far-field chunk mask of the unrolled pair kernel
+    const bool far = !solo && N_ > 1 && M_ <= kMaxPairOrder && N_ <= kPairFarMaxN;
+    L.fmask = add(far ? (size_t)N_ * ((N_ + 63) / 64) : 0);
     L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
         const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
@@ -352,6 +355,8 @@ size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs*
     bufs.p_part = (!solo && N_ > 1 && M_ <= kMaxPairOrder && pair_split_groups(N_) > 1) ? (double*)(b + L.ppart)
                                                                                           : nullptr;
     bufs.pair_groups = 0;
+    bufs.far_mask = (!solo && N_ > 1 && M_ <= kMaxPairOrder && N_ <= kPairFarMaxN) ? (unsigned char*)(b + L.fmask)
+                                                                                  : nullptr;
     bufs.s_pad = (double*)(b + L.spad);
     for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
     bufs.accD = mx ? (double*)(b + L.accd) : nullptr;

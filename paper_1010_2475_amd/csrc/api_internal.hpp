@@ -64,10 +64,7 @@ const DevTables* find_device_tables(int M);
 size_t stage_layout(char* base, int N, int M, bool need_dd, bool solo, StageBufs* bufs, DevClock** clock,
                     double** par);
 
-// per-kernel timing (mmvm_timing_enable); no-ops when disabled
-bool timing_on();
-void* timing_begin(hipStream_t st);
-void timing_end(void* tok, const char* name, hipStream_t st);
+// per-kernel timing (mmvm_timing_enable): timing_on, timing_begin, timing_end in kernels.hpp
 // replays of captured stepping graphs since the process started
 void count_graph_replays(int64_t n);
 int64_t graph_replays();

@@ -59,6 +59,7 @@ struct StageBufs {
     double* s_pair;        // [N][KG] pair velocity-derivative table
     double* p_part;        // [N][groups][KG] partial pair tables of split source groups (or null)
     int pair_groups;       // > 1: the pair table is the sum of these partial tables (set per stage)
+    unsigned char* far_mask;  // [N][ceil(N / 64)] far-field chunks of the pair kernel (or null)
     double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
@@ -147,7 +148,12 @@ struct PairShape {
     int split = 1, tpb = 4;
     int kind = 0, groups = 1;
     int f64 = 0;
+    int far = 0;  // kind 0: chunks of far pairs go to the multipole kernel k_pair_far
 };
+// the far-field split needs a mask of N x ceil(N / 64) bytes: offered up to this N
+constexpr int kPairFarMaxN = 16384;
+// from this N the tuner only offers shapes with the far split
+constexpr int kPairFarAlwaysN = 1024;
 constexpr int kPairMaxThreads = 256;  // the kernel keeps up to 256 VGPRs + AGPRs per lane
 // largest N * groups of a split launch with groups > 1
 constexpr int kPairSplitMaxPartials = 1024;
@@ -267,6 +273,11 @@ struct TimingSlot {
     bool used = false;
 };
 TimingSlot*& timing_slot();
+// per-kernel timing (mmvm_timing_enable); no-ops when disabled: the first kernel
+// launched between begin and end is timed under `name`
+bool timing_on();
+void* timing_begin(hipStream_t st);
+void timing_end(void* tok, const char* name, hipStream_t st);
 
 template <typename F, typename... Args>
 inline void launch_kernel(F kernel, const dim3& grid, const dim3& block, std::uint32_t shmem, hipStream_t st,

@@ -86,16 +86,30 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
     // split over 1, 2 or 4 of them (each keeping at least 32 sources)
     // (for the mixed precision also the FP64 variant of the unrolled kernel: a
     // key may run FP64 wherever that is faster)
+    // and each of those with the far-field chunks split off to the multipole kernel
+    // The far split decides per 64-source chunk at run time, so it costs a dense
+    // field only its mask (one ballot and byte per chunk) and a scan of that mask,
+    // while a key (tuned on one geometry) may later see a dilute one: from
+    // kPairFarAlwaysN vortices every candidate splits the far field off.
+    // MMVM_PAIR_FAR=0 / 1 restricts the candidates to either form.
+    int far_lo = 0, far_hi = B.far_mask ? 1 : 0;
+    if (far_hi && B.N >= kPairFarAlwaysN) far_lo = 1;
+    if (const char* f = std::getenv("MMVM_PAIR_FAR")) {
+        if (f[0] == '0') far_lo = far_hi = 0;
+        else if (f[0] == '1' && B.far_mask) far_lo = far_hi = 1;
+    }
     std::vector<PairShape> cand;
-    for (int f64 = 0; f64 <= (f32 ? 1 : 0); ++f64)
-        for (int split = 1; split <= 4; split <<= 1)
-            for (int tpb = 1; tpb <= 4; tpb <<= 1) {
-                PairShape s;
-                s.split = split;
-                s.tpb = tpb;
-                s.f64 = f64;
-                if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
-            }
+    for (int far = far_lo; far <= far_hi; ++far)
+        for (int f64 = 0; f64 <= (f32 ? 1 : 0); ++f64)
+            for (int split = 1; split <= 4; split <<= 1)
+                for (int tpb = 1; tpb <= 4; tpb <<= 1) {
+                    PairShape s;
+                    s.split = split;
+                    s.tpb = tpb;
+                    s.f64 = f64;
+                    s.far = far;
+                    if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
+                }
     // the few-vortex kernel (16 lanes per pair, FP64)
     if (B.N >= 2) {
         PairShape s;
@@ -115,7 +129,8 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
             const double us = time_pair(T, B, cur, f32, s, st, e0, e1);
             if (us < 0.0) continue;
             ++best.candidates;
-            if (s.kind == def.kind && s.split == def.split && s.tpb == def.tpb && s.f64 == def.f64) best.us_def = us;
+            if (s.kind == def.kind && s.split == def.split && s.tpb == def.tpb && s.f64 == def.f64 && s.far == def.far)
+                best.us_def = us;
             if (best.us < 0.0 || us < best.us) {
                 best.us = us;
                 best.shape = s;
@@ -153,11 +168,11 @@ mmvm_status mmvm_autotune_report(char* buf, size_t cap, size_t* needed)
         for (const auto& kv : g_pair) {
             const PairEntry& e = kv.second;
             std::snprintf(line, sizeof(line),
-                          "pair order=%d prec=%s n<=%d kind=%d split=%d tpb=%d groups=%d f64=%d us=%.3f "
+                          "pair order=%d prec=%s n<=%d kind=%d split=%d tpb=%d groups=%d f64=%d far=%d us=%.3f "
                           "default_us=%.3f candidates=%d\n",
                           std::get<0>(kv.first), std::get<1>(kv.first) ? "mixed" : "fp64", std::get<2>(kv.first),
-                          e.shape.kind, e.shape.split, e.shape.tpb, e.shape.groups, e.shape.f64, e.us, e.us_def,
-                          e.candidates);
+                          e.shape.kind, e.shape.split, e.shape.tpb, e.shape.groups, e.shape.f64, e.shape.far, e.us,
+                          e.us_def, e.candidates);
             out += line;
         }
     }

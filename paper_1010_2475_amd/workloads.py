@@ -23,6 +23,14 @@ Workloads (all synthetic; the paper uses no dataset):
                      higher moments 0.
   two_clusters       2 x N/2 vortices at (-2,0) and (2,0), x ~ N(centre, I),
                      circulation 1/(N/2) each, core scales U[0.2,0.5].
+  dilute_multi       N vortices uniform over a square of mean spacing 2
+                     (most pairs in each other's far field).
+  tripole_coarse     the large quadrupole perturbation (lambda0 = 1, delta = 0.25,
+                     Re 1000) on a 6 x 6 grid of vortices over [-1,1]^2 of core
+                     lambda0, circulations omega_0(x_j) times the node area
+                     (eq:blurredIC), orders 0 or 2 (section "Tripole Relaxation").
+  tripole_reference  that blurred initial vorticity as one particle of order 24
+                     (moments of the 36 Gaussians about the centre).
   request_stream     Poisson arrivals of mixed single / multi-vortex solves.
 """
 import math
@@ -124,6 +132,60 @@ def two_clusters(N=4096, M=4, Re=2000.0, seed=4, sep=4.0, sigma=1.0, dt=1e-3, st
     mom[:h, 0] = 1.0 / h
     mom[h:, 0] = 1.0 / (N - h)
     return Workload("two_clusters", M, x, mom, lam0, 1.0 / Re, dt, steps)
+
+
+def dilute_multi(N=4096, M=4, Re=1000.0, seed=6, spacing=2.0, dt=1e-3, steps=100):
+    """N vortices spread uniformly over a square whose mean spacing is
+    `spacing` (most pairs far apart relative to their cores), circulations
+    U[-1,1], core scales U[0.2,0.5], higher moments zero: the dilute field on
+    which the pair interaction's far field dominates."""
+    rng = np.random.default_rng(seed)
+    half = 0.5 * spacing * math.sqrt(N)
+    x = rng.uniform(-half, half, (N, 2))
+    gam = rng.uniform(-1.0, 1.0, N)
+    gam[np.abs(gam) < 1e-3] = 1e-3
+    lam0 = rng.uniform(0.2, 0.5, N)
+    mom = np.zeros((N, K_of(M)))
+    mom[:, 0] = gam
+    return Workload("dilute_multi", M, x, mom, lam0, 1.0 / Re, dt, steps)
+
+
+def tripole_coarse(M=2, delta=0.25, lam0=1.0, Re=1000.0, n=6, dt=1e-3, steps=16000):
+    """The large quadrupole perturbation of the Lamb-Oseen vortex on a coarse
+    n x n grid of vortex centres over [-1, 1]^2 (section "Tripole Relaxation",
+    eq:blurredIC): circulation M^j_00 = omega_0(x_j) * (node area), higher
+    moments zero, every element of the one core size lambda0 (the paper's
+    multi-vortex equations take one core size for all elements, and it states
+    no other for this grid).  omega_0 = phi00 + 4 delta (phi20 - phi02)
+    (eq:perturbM2) = phi00 (1 + 16 delta (x1^2 - x2^2) / lambda0^4), with
+    phi00 = exp(-|x|^2 / lambda0^2) / (pi lambda0^2) (eq:phi00) and
+    phi_k = D^k phi00 (eq:Hermitedef)."""
+    g = np.linspace(-1.0, 1.0, n)
+    hx = g[1] - g[0]
+    X1, X2 = np.meshgrid(g, g, indexing="ij")
+    x = np.stack([X1.ravel(), X2.ravel()], axis=1)
+    r2 = (x ** 2).sum(1)
+    phi00 = np.exp(-r2 / lam0 ** 2) / (math.pi * lam0 ** 2)
+    omega0 = phi00 * (1.0 + 16.0 * delta * (x[:, 0] ** 2 - x[:, 1] ** 2) / lam0 ** 4)
+    mom = np.zeros((n * n, K_of(M)))
+    mom[:, 0] = omega0 * hx * hx
+    return Workload("tripole_coarse", M, x, mom, np.full(n * n, lam0), 1.0 / Re, dt, steps)
+
+
+def tripole_reference(M=24, delta=0.25, lam0=1.0, Re=1000.0, n=6, dt=1e-3, steps=16000):
+    """The same blurred initial vorticity (the n x n grid of eq:blurredIC) as
+    one particle of order M at the centre (the paper's order-24 reference
+    solution of the identical initial conditions).  The elements share the
+    particle's core, so each Gaussian's expansion about the centre is its
+    Taylor series, phi00(x - a) = sum_k (-a)^k / k! D^k phi00(x), and the
+    particle's moments are M_k = sum_j Gamma_j (-a_j1)^{k1} (-a_j2)^{k2} / (k1! k2!)
+    (first moments zero by the grid's symmetry)."""
+    c = tripole_coarse(M=0, delta=delta, lam0=lam0, Re=Re, n=n, dt=dt, steps=steps)
+    mom = np.zeros((1, K_of(M)))
+    for (k1, k2) in multi_indices(M):
+        mom[0, index(k1, k2)] = np.sum(c.mom[:, 0] * (-c.x[:, 0]) ** k1 * (-c.x[:, 1]) ** k2
+                                       / (math.factorial(k1) * math.factorial(k2)))
+    return Workload("tripole_reference", M, np.zeros((1, 2)), mom, [lam0], 1.0 / Re, dt, steps)
 
 
 def request_stream(n=2000, seed=5, mean_gap=5e-3, dt=1e-3):

@@ -675,3 +675,36 @@ def test_high_order_stepping_matches_oracle_golden(env, prec):
         err = normwise(w.M, lam_t, np.array([c["mom"]]), m_g)
         assert err <= tol, (c["M"], err)
         assert m_g[0, 0] == w.mom[0, 0]
+
+
+@pytest.mark.parametrize("M,prec", [(4, 0), (6, 0), (4, 1)])
+def test_far_field_dilute_matches_oracle(env, orc, M, prec):
+    """A dilute field (mean spacing 2, cores 0.2-0.5): most 64-source chunks of
+    a target are entirely beyond the far-field threshold, and the tuned shape
+    sends them to the multipole kernel.  Sampled rows against the oracle, and
+    the tuned result against the default shape (no far-field split) to
+    rounding."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.dilute_multi(N=2000, M=M, seed=60 + M)
+    structure(w, 61 + M)
+    t = 0.2
+    mm.autotune_enable(False)
+    try:
+        _, d_def = gpu_rhs(env, w, t, prec)
+    finally:
+        mm.autotune_enable(True)
+    dx_g, dm_g = gpu_rhs(env, w, t, prec)
+    rep = mm.autotune_report()
+    print(rep, flush=True)
+    js = [0, 999, 1999]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, dxr = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    tol = FP64_TOL if prec == 0 else MIXED_TOL
+    gam = w.mom[js, 0]
+    dx_r = dxr.reshape(3, w.K, 2)[:, 0, :]
+    assert normwise(w.M, lam_t[js], d.reshape(3, w.K), dm_g[js], gam, dx_r) <= tol
+    assert np.abs(dx_g[js] - dx_r).max() <= tol * np.abs(dx_r).max()
+    assert normwise(w.M, lam_t, d_def, dm_g, w.mom[:, 0], dx_g) <= (1e-13 if prec == 0 else 2 * MIXED_TOL)

@@ -1,0 +1,71 @@
+"""The coarse-grid tripole workload (section "Tripole Relaxation"): the
+6 x 6 grid of vortices of eq:blurredIC against the oracle, and the paper's
+finding behind tab:error, that second-order moments bring the coarse grid
+closer to the high-order single-particle solution than plain Gaussians."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1010_2475_amd import mmvm
+    mmvm.lib()
+    return torch, mmvm
+
+
+@pytest.mark.parametrize("M", [0, 2])
+def test_tripole_coarse_grid_matches_oracle(env, orc, M):
+    from paper_1010_2475_amd import workloads as wl
+    from test_gpu_parity import gpu_rhs, gpu_step, normwise
+    w = wl.tripole_coarse(M=M)
+    dx_g, dm_g = gpu_rhs(env, w, 0.0, 0)
+    dx_r, dm_r = orc.rhs(M, w.nu, w.lam0, 0.0, w.x, w.mom)
+    assert np.abs(dx_g - dx_r).max() <= 1e-12 * np.abs(dx_r).max()
+    if M > 0:
+        assert normwise(M, w.lam0, dm_r, dm_g, w.mom[:, 0], dx_r) <= 1e-12
+    steps = 60
+    x_g, m_g = gpu_step(env, w, 0.0, steps, 0)
+    x_r, m_r = orc.rk4(M, w.nu, w.lam0, 0.0, w.dt, steps, w.x, w.mom)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * steps * w.dt)
+    assert np.abs(x_g - x_r).max() <= 1e-12 * max(1.0, np.abs(x_r).max())
+    assert normwise(M, lam_t, m_r, m_g) <= 1e-12
+
+
+def test_second_moments_beat_plain_gaussians(env):
+    """At t = 1: relative L2 and Linf errors of the order-0 and order-2 coarse
+    grids against the order-24 single particle of the same blurred initial
+    vorticity, on a 256 x 256 grid over [-4, 4]^2; order 2 is the closer (the
+    paper's tab:error, about 4x there)."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    T, h, n = 1.0, 8.0 / 255, 256
+
+    def omega(w):
+        X = torch.tensor(w.x, device=dev)
+        Mo = torch.tensor(w.mom, device=dev)
+        steps = int(round(T / w.dt))
+        print("tripole M=%d N=%d steps=%d" % (w.M, w.N, steps), flush=True)
+        mm.step(w.M, w.nu, w.lam0, 0.0, w.dt, steps, X, Mo, 0)
+        om = torch.zeros((n, n), dtype=torch.float64, device=dev)
+        mm.vorticity_grid(w.M, w.nu, w.lam0, T, X, Mo, -4.0, -4.0, h, n, n, om)
+        mm.sync()
+        return om.cpu().numpy()
+
+    ref = omega(wl.tripole_reference())
+    errs = {}
+    for M in (0, 2):
+        d = omega(wl.tripole_coarse(M=M)) - ref
+        errs[M] = (np.sqrt((d ** 2).sum() / (ref ** 2).sum()), np.abs(d).max() / np.abs(ref).max())
+    print("errors at t=1", errs, flush=True)
+    assert errs[2][0] < errs[0][0] and errs[2][1] < errs[0][1], errs

@@ -601,3 +601,30 @@ def test_dopri5_converges_to_the_solution(orc):
     assert np.abs(mo - mr).max() <= 1e-9 * np.abs(mr).max()
     assert np.abs(xo - xr).max() <= 1e-9
     assert np.array_equal(mo[:, 0], mom[:, 0])  # circulation exactly conserved
+
+
+def test_tripole_coarse_grid_and_its_single_particle(orc):
+    """eq:blurredIC: each coarse circulation is the vorticity eq:perturbM2 at
+    the node (the oracle's Hermite expansion of the exact order-2 particle)
+    times the node area; the order-24 particle of the same blurred field
+    reproduces the sum of the 36 Gaussians (evaluated here in closed form)."""
+    from paper_1010_2475_amd import workloads as wl
+    exact = wl.single_quadrupole(M=2, delta=0.25, lam0=1.0)
+    area = (2.0 / 5) ** 2
+    for M in (0, 2):
+        c = wl.tripole_coarse(M=M)
+        assert c.N == 36 and np.all(c.mom[:, 1:] == 0.0) and np.all(c.lam0 == 1.0)
+        om = orc.vorticity(2, exact.nu, exact.lam0, 0.0, exact.x, exact.mom, c.x[:, 0], c.x[:, 1])
+        assert np.allclose(c.mom[:, 0] / area, om, rtol=1e-12, atol=1e-14)
+    # negative where x2^2 - x1^2 > 1/4 (delta = 1/4, lambda0 = 1): 12 of the 36 nodes
+    assert (om < 0).sum() == 12
+    ref = wl.tripole_reference()
+    assert ref.M == 24 and ref.N == 1
+    assert abs(ref.mom[0, 0] - c.mom[:, 0].sum()) <= 1e-15 and np.all(np.abs(ref.mom[0, 1:3]) <= 1e-15)
+    g = np.linspace(-4.0, 4.0, 81)
+    P1, P2 = [a.ravel() for a in np.meshgrid(g, g, indexing="ij")]
+    blob = np.zeros_like(P1)
+    for (a1, a2), gam in zip(c.x, c.mom[:, 0]):
+        blob += gam * np.exp(-((P1 - a1) ** 2 + (P2 - a2) ** 2)) / math.pi
+    got = orc.vorticity(24, ref.nu, ref.lam0, 0.0, ref.x, ref.mom, P1, P2)
+    assert np.abs(got - blob).max() <= 1e-6 * np.abs(blob).max()
