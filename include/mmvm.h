@@ -203,8 +203,16 @@ mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launc
 
 /* ---------------------------------------------------------------------------
  * Launch-shape autotuning of the pair kernel (the all-pairs interaction of
- * eq:Final_CrossCoef): how many wavefronts share the sources of one target
- * and how many targets a workgroup holds.  On by default (the environment
+ * eq:Final_CrossCoef): how many wavefronts share the sources of one target,
+ * how many targets a workgroup holds, FP32 or FP64 arithmetic for the mixed
+ * precision, the few-vortex kernel (16 lanes per pair), and whether 64-source
+ * chunks lying wholly in a target's far field (beyond the Gaussian cores: the
+ * pair field is then the harmonic multipole of the source) go to the cheaper
+ * far-field kernel.  From 1024 vortices (orders 0-6) the sources of each call
+ * are sorted in space (Morton order of the call's initial positions) and
+ * every candidate uses the far-field split, which decides per chunk at run
+ * time; the environment variable MMVM_PAIR_FAR=0 (or 1) restricts the
+ * candidates to shapes without (with) it.  On by default (the environment
  * variable MMVM_AUTOTUNE=0 starts a process with it off).  The first launch
  * for a new key (order, precision, vortex count rounded up to a power of two)
  * times every candidate shape on the caller's stream with the caller's

@@ -92,6 +92,117 @@ __global__ __launch_bounds__(256) void k_alpha_dense_clear(StageBufs B, int M)
     }
 }
 
+// Spatial order of the pair kernels' sources: the vortices of one call
+// sorted by the Morton code of their positions at the call's start, so that
+// consecutive chunks of 64 sources are compact (a target's near chunks are
+// few, its far chunks are skipped as wholes).  One workgroup: bounding box of
+// the finite positions, 16-bit grid coordinates interleaved into a 32-bit
+// code, the vortex index below it (unique keys: a deterministic order),
+// bitonic sort of NP (a power of two >= N) keys in LDS.  Positions move within
+// a call; the order only has to stay good, not exact.
+constexpr int kSortThreads = 1024;
+
+__device__ __forceinline__ unsigned spread_bits16(unsigned v)
+{
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_sources(int N, int NP, const double* __restrict__ x,
+                                                               int* __restrict__ rank, int* __restrict__ perm)
+{
+    extern __shared__ unsigned long long skey[];  // [NP]
+    __shared__ double red[4][kSortThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double lo1 = INFINITY, hi1 = -INFINITY, lo2 = INFINITY, hi2 = -INFINITY;
+    for (int j = tid; j < N; j += kSortThreads) {
+        const double a = x[2 * j], b = x[2 * j + 1];
+        if (isfinite(a) && isfinite(b)) {
+            lo1 = fmin(lo1, a);
+            hi1 = fmax(hi1, a);
+            lo2 = fmin(lo2, b);
+            hi2 = fmax(hi2, b);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo1 = fmin(lo1, __shfl_xor(lo1, off, 64));
+        hi1 = fmax(hi1, __shfl_xor(hi1, off, 64));
+        lo2 = fmin(lo2, __shfl_xor(lo2, off, 64));
+        hi2 = fmax(hi2, __shfl_xor(hi2, off, 64));
+    }
+    if (lane == 0) {
+        red[0][wv] = lo1;
+        red[1][wv] = hi1;
+        red[2][wv] = lo2;
+        red[3][wv] = hi2;
+    }
+    __syncthreads();
+    lo1 = red[0][0];
+    hi1 = red[1][0];
+    lo2 = red[2][0];
+    hi2 = red[3][0];
+    for (int w = 1; w < kSortThreads / 64; ++w) {
+        lo1 = fmin(lo1, red[0][w]);
+        hi1 = fmax(hi1, red[1][w]);
+        lo2 = fmin(lo2, red[2][w]);
+        hi2 = fmax(hi2, red[3][w]);
+    }
+    const double sc1 = hi1 > lo1 ? 65535.0 / (hi1 - lo1) : 0.0;
+    const double sc2 = hi2 > lo2 ? 65535.0 / (hi2 - lo2) : 0.0;
+    for (int p = tid; p < NP; p += kSortThreads) {
+        unsigned long long key = ~0ull;
+        if (p < N) {
+            const double a = x[2 * p], b = x[2 * p + 1];
+            unsigned q1 = 0, q2 = 0;
+            if (isfinite(a) && isfinite(b)) {
+                q1 = (unsigned)fmin(65535.0, fmax(0.0, (a - lo1) * sc1));
+                q2 = (unsigned)fmin(65535.0, fmax(0.0, (b - lo2) * sc2));
+            }
+            const unsigned code = spread_bits16(q1) | (spread_bits16(q2) << 1);
+            key = ((unsigned long long)code << 32) | (unsigned)p;
+        }
+        skey[p] = key;
+    }
+    __syncthreads();
+    // bitonic network: each pass compare-exchanges NP/2 disjoint pairs (i, i + jj)
+    for (int k = 2; k <= NP; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = tid; t < (NP >> 1); t += kSortThreads) {
+                const int i = 2 * jj * (t / jj) + (t % jj), l = i + jj;
+                const unsigned long long a = skey[i], b = skey[l];
+                if ((a > b) == ((i & k) == 0)) {
+                    skey[i] = b;
+                    skey[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int p = tid; p < N; p += kSortThreads) {
+        const int j = (int)(skey[p] & 0xffffffffull);
+        perm[p] = j;
+        rank[j] = p;
+    }
+}
+
+hipError_t launch_sort_sources(const StageBufs& B, const double* x, hipStream_t st)
+{
+    if (!B.rank || !B.perm || B.N > kPairFarMaxN) return hipErrorInvalidValue;
+    int NP = 1;
+    while (NP < B.N) NP <<= 1;
+    const size_t shmem = sizeof(unsigned long long) * (size_t)NP;
+    // the limit is set once per device: for the largest sort (kPairFarMaxN keys, 128 KB)
+    const hipError_t e = lds_limit_once((const void*)k_sort_sources,
+                                        sizeof(unsigned long long) * (size_t)kPairFarMaxN, "k_sort_sources");
+    if (e != hipSuccess) return e;
+    launch_kernel(k_sort_sources, dim3(1), dim3(kSortThreads), (std::uint32_t)shmem, st, B.N, NP, x,
+                  (int*)B.rank, (int*)B.perm);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N, int K, const double* __restrict__ xin,
                                               const double* __restrict__ min_, const double* __restrict__ lam0sq,
                                               double t, double* __restrict__ xs, double* __restrict__ ys,
@@ -113,14 +224,20 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
         }
         alpha[idx] = a;
         store_dense_alpha(B, cur, M, j, sk - (k - sk * (sk + 1) / 2), k - sk * (sk + 1) / 2, a);
-        if (alphaT) alphaT[(long)k * N + j] = a;
-        if (alphaT32) alphaT32[(long)k * N + j] = (float)a;
+        const int src = B.rank ? B.rank[j] : j;  // the pair kernels' source index
+        if (alphaT) alphaT[(long)k * N + src] = a;
+        if (alphaT32) alphaT32[(long)k * N + src] = (float)a;
         if (!isfinite(mk)) atomicOr(flag, 2);
         if (k == 0) {
             lam2[j] = l2;
             double x0 = xin[2 * j], x1 = xin[2 * j + 1];
             xs[2 * j] = x0;
             xs[2 * j + 1] = x1;
+            if (B.rank) {
+                B.lam2S[cur][src] = l2;
+                B.xsS[2 * src] = x0;
+                B.xsS[2 * src + 1] = x1;
+            }
             if (B.interact && mk == 0.0) atomicOr(flag, 1);
             if (!isfinite(x0) || !isfinite(x1)) atomicOr(flag, 2);
         }
@@ -130,6 +247,10 @@ __global__ __launch_bounds__(256) void k_prep(StageBufs B, int cur, int M, int N
 hipError_t launch_prep(const DevTables& T, const StageBufs& B, int cur, const double* xin, const double* min_,
                        double t, bool need_pair, bool need_f32, hipStream_t st)
 {
+    if (B.rank) {
+        const hipError_t e = launch_sort_sources(B, xin, st);
+        if (e != hipSuccess) return e;
+    }
     long total = (long)B.N * T.K;
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
@@ -184,8 +305,9 @@ __device__ __forceinline__ void emit_moment(const StageBufs& B, const StageArgs&
     }
     if (S.want_pair) {
         // FP64 always (the mixed path may run the FP64 pair kernel), FP32 for the mixed kernel
-        B.alphaT[nx][(long)k * B.N + j] = a;
-        if (S.want_f32) B.alphaT32[nx][(long)k * B.N + j] = (float)a;
+        const int src = B.rank ? B.rank[j] : j;
+        B.alphaT[nx][(long)k * B.N + src] = a;
+        if (S.want_f32) B.alphaT32[nx][(long)k * B.N + src] = (float)a;
     }
 }
 
@@ -197,9 +319,17 @@ __device__ __forceinline__ void emit_position(const StageBufs& B, const StageArg
         S.dx[2 * j + 1] = xd2;
         return;
     }
-    B.xs[2 * j] = rk4_update(S.stage, S.dt, S.x + 2 * j, B.accx + 2 * j, xd1);
-    B.xs[2 * j + 1] = rk4_update(S.stage, S.dt, S.x + 2 * j + 1, B.accx + 2 * j + 1, xd2);
+    const double x0 = rk4_update(S.stage, S.dt, S.x + 2 * j, B.accx + 2 * j, xd1);
+    const double x1 = rk4_update(S.stage, S.dt, S.x + 2 * j + 1, B.accx + 2 * j + 1, xd2);
+    B.xs[2 * j] = x0;
+    B.xs[2 * j + 1] = x1;
     B.lam2[1 - S.cur][j] = lam2_next;
+    if (B.rank) {
+        const int src = B.rank[j];
+        B.xsS[2 * src] = x0;
+        B.xsS[2 * src + 1] = x1;
+        B.lam2S[1 - S.cur][src] = lam2_next;
+    }
 }
 
 // ---------------------------------------------------------------------------

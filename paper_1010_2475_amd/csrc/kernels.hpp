@@ -59,7 +59,14 @@ struct StageBufs {
     double* s_pair;        // [N][KG] pair velocity-derivative table
     double* p_part;        // [N][groups][KG] partial pair tables of split source groups (or null)
     int pair_groups;       // > 1: the pair table is the sum of these partial tables (set per stage)
-    unsigned char* far_mask;  // [N][ceil(N / 64)] far-field chunks of the pair kernel (or null)
+    unsigned char* far_mask;  // [N][pair_mask_stride(N)] far-field chunks of the pair kernel (or null)
+    // the pair kernels' sources in spatial order (from kPairFarAlwaysN vortices):
+    // source p is vortex perm[p], vortex j is source rank[j] (null: caller order)
+    const int* rank;
+    const int* perm;
+    double* xsS;           // [N][2] stage positions of the sources (= xs when not sorted)
+    double* lam2S[2];      // [N] lambda^2 of the sources (= lam2 when not sorted)
+    // alphaT / alphaT32 hold the sources in the same order
     double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
@@ -152,8 +159,19 @@ struct PairShape {
 };
 // the far-field split needs a mask of N x ceil(N / 64) bytes: offered up to this N
 constexpr int kPairFarMaxN = 16384;
-// from this N the tuner only offers shapes with the far split
+// highest order whose mixed-precision pair kernel keeps FP32 shells: there the
+// normwise error stays below 1e-6 for every spectrum measured, flat included
+// (6e-7); at orders 5 and 6 the FP32 shells reach 3e-6 (decaying spectra) to
+// 3.5e-5 (flat), so the mixed path runs them in FP64
+constexpr int kPairF32MaxOrder = 4;
+// from this N the tuner only offers shapes with the far split, and the sources
+// are sorted in space
 constexpr int kPairFarAlwaysN = 1024;
+// bytes of one target's row of the far-chunk mask (chunks of 64 sources, rows
+// padded to 8 bytes for 64-bit loads)
+constexpr int pair_mask_stride(int N) { return (((N + 63) >> 6) + 7) & ~7; }
+// sorts the sources of a stage in space (rank, perm) from the call's positions
+hipError_t launch_sort_sources(const StageBufs& B, const double* x, hipStream_t st);
 constexpr int kPairMaxThreads = 256;  // the kernel keeps up to 256 VGPRs + AGPRs per lane
 // largest N * groups of a split launch with groups > 1
 constexpr int kPairSplitMaxPartials = 1024;

@@ -66,11 +66,17 @@ constexpr double pair_far_w(int P) { return 50.0 + 2.5 * P; }
 // FAR: a wavefront whose pairs of one 64-source chunk are all beyond the
 // threshold skips them and marks the chunk in farmask[j][chunk] (0 otherwise);
 // k_pair_far adds those pairs afterwards.
+// Targets j come from (xt, lam2t) in the caller's order; sources from (xs,
+// lam2, aT) in the sources' order, where target j is source rank[j] (rank null:
+// the same order).
 template <int M, typename R, bool FAR>
-__global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, const double* __restrict__ xs,
+__global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, const double* __restrict__ xt,
+                                                          const double* __restrict__ lam2t,
+                                                          const double* __restrict__ xs,
                                                           const double* __restrict__ lam2, const R* __restrict__ aT,
                                                           double* __restrict__ spair,
-                                                          unsigned char* __restrict__ farmask)
+                                                          unsigned char* __restrict__ farmask,
+                                                          const int* __restrict__ rank)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -93,9 +99,10 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     const bool live = j < N;  // uniform per wavefront; every wave reaches the barrier below
     const int jc = live ? j : 0;
 
-    const double xj1 = xs[2 * jc], xj2 = xs[2 * jc + 1], lj2 = lam2[jc];
+    const double xj1 = xt[2 * jc], xj2 = xt[2 * jc + 1], lj2 = lam2t[jc];
     const double ilj = 1.0 / sqrt(lj2);
     const double lj = lj2 * ilj;
+    const int self = rank ? rank[jc] : jc;
 
     double acc[KG];
     R acc32[F32 ? KG : 1];
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     int pending = 0;
 
     for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split) {
-        if (jp == j) continue;
+        if (jp == self) continue;
         const double lp2 = lam2[jp];
         const double c = lj2 + lp2;
         const double isc = 1.0 / sqrt(c);
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
         const double w = s1 * s1 + s2 * s2;
         if constexpr (FAR) {
             const bool all_far = __all(w > pair_far_w(P));  // uniform over the wavefront's active lanes
-            farmask[(long)j * ((N + 63) >> 6) + (jp >> 6)] = all_far ? 1 : 0;
+            farmask[(long)j * pair_mask_stride(N) + (jp >> 6)] = all_far ? 1 : 0;
             if (all_far) continue;
         }
         const double e1 = exp(-s1 * s1), e2 = exp(-s2 * s2);
@@ -273,89 +280,124 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     }
 }
 
-// The pairs of the chunks marked far, one wavefront per target, added to the
-// pair table after the near kernel (FP64; the same multipole form in both
-// precisions):  Q_s = sum_{|m| = s} alpha'_m i^{m2},  T_p = sum_s Q_s H_{s+p},
-// S[g] += 2 Re(i^{g2} T_{|g|}),  with H_n generated shell by shell.
+// The pairs of the chunks marked far, one wavefront per target (lanes over the
+// 64 sources of a chunk), added to the pair table after the near kernel (FP64
+// in both precisions; the same multipole form for every shape):
+//   Q_s = sum_{|m| = s} alpha'_m i^{m2},  T_p = sum_s Q_s H_{s+p},
+//   S[g] += 2 Re(i^{g2} T_{|g|}),  H_n = hol[n] (lambda_j / Delta z)^n,
+// Delta z = (x^j - x^{j'})_1 + i (x^j - x^{j'})_2, generated shell by shell.
+// The wavefront reads the flags of 64 chunks at once (lane c: chunk c) and
+// visits the set ones only, so a target with no far chunk costs one load.
+// A workgroup of kFarWaves wavefronts takes one target, wavefront q the far
+// chunks c = q mod kFarWaves (the far chunks of a target tend to be runs of
+// consecutive sorted chunks: the targets at the edge of a dense region carry
+// many, the others none); the wavefront sums meet in LDS in wavefront order.
+constexpr int kFarWaves = 4;
+constexpr int kFarThreads = 64 * kFarWaves;
+
 template <int M>
-__global__ __launch_bounds__(256) void k_pair_far(int N, const double* __restrict__ xs,
-                                                  const double* __restrict__ lam2, const double* __restrict__ aT,
-                                                  const unsigned char* __restrict__ farmask,
-                                                  double* __restrict__ spair)
+__global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* __restrict__ xt,
+                                                          const double* __restrict__ lam2t,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ lam2,
+                                                          const double* __restrict__ aT,
+                                                          const unsigned char* __restrict__ farmask,
+                                                          const int* __restrict__ rank, double* __restrict__ spair)
 {
-    constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
     constexpr int GM = M == 0 ? 1 : 2 * M;
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
-    (void)K;
-    const int lane = threadIdx.x & 63, j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (j >= N) return;  // uniform per wavefront; no barrier below
-    const int nch = (N + 63) >> 6;
-    const double xj1 = xs[2 * j], xj2 = xs[2 * j + 1], lj2 = lam2[j];
+    __shared__ double red[kFarWaves][2 * GM + 2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = blockIdx.x;
+    // chunk c0 + b of a group of 64 belongs to this wavefront when b = wave mod kFarWaves
+    unsigned long long mine = 0;
+    for (int b = wave; b < 64; b += kFarWaves) mine |= 1ull << b;
+    const int stride = pair_mask_stride(N), nch = (N + 63) >> 6;
+    const unsigned char* row = farmask + (long)j * stride;
+    const int self = rank ? rank[j] : j;
+    const double xj1 = xt[2 * j], xj2 = xt[2 * j + 1], lj2 = lam2t[j];
     const double ilj = 1.0 / sqrt(lj2), lj = lj2 * ilj;
-    double acc[KG];
-    sfor<0, KG>([&](auto g) { acc[g] = 0.0; });
-    for (int c = 0; c < nch; ++c) {
-        if (!farmask[(long)j * nch + c]) continue;  // uniform per wavefront
-        const int jp = c * 64 + lane;
-        if (jp >= N || jp == j) continue;
-        const double lp2 = lam2[jp];
-        const double isc = 1.0 / sqrt(lj2 + lp2);
-        const double s1 = (xj1 - xs[2 * jp]) * isc, s2 = (xj2 - xs[2 * jp + 1]) * isc;
-        const double w = s1 * s1 + s2 * s2;
-        const double ratio = sqrt(lp2) * ilj, tz = lj * isc / w;
-        const double ur = tz * s1, ui = -tz * s2;  // tau / z
-        double Qr[M + 1], Qi[M + 1];
-        {
-            double rp = 1.0;
-            sfor<0, M + 1>([&](auto s) {
-                double qr = 0.0, qi = 0.0;
-                sfor<0, s + 1>([&](auto m2) {
-                    const double a = aT[(long)ctri(s - m2, m2) * N + jp] * rp;
-                    if constexpr (m2 % 4 == 0) qr += a;
-                    else if constexpr (m2 % 4 == 1) qi += a;
-                    else if constexpr (m2 % 4 == 2) qr -= a;
-                    else qi -= a;
+    // T_p summed over the lane's pairs (S is linear in T: expanded to the
+    // entries g once, after the wavefront sum)
+    double Tr[GM + 1], Ti[GM + 1];
+    sfor<1, GM + 1>([&](auto p) { Tr[p] = 0.0; Ti[p] = 0.0; });
+    int any = 0;  // this wavefront had far chunks
+    for (int c0 = 0; c0 < nch; c0 += 64) {
+        const bool flag = c0 + lane < nch && row[c0 + lane] != 0;
+        unsigned long long far = __ballot(flag) & mine;  // uniform per wavefront
+        any |= far != 0;
+        while (far) {
+            const int c = c0 + __builtin_ctzll(far);
+            far &= far - 1;
+            const int jp = c * 64 + lane;
+            if (jp >= N || jp == self) continue;
+            const double lp2 = lam2[jp];
+            const double isc = 1.0 / sqrt(lj2 + lp2);
+            const double s1 = (xj1 - xs[2 * jp]) * isc, s2 = (xj2 - xs[2 * jp + 1]) * isc;
+            const double w = s1 * s1 + s2 * s2;
+            const double ratio = sqrt(lp2) * ilj, tz = lj * isc / w;
+            const double ur = tz * s1, ui = -tz * s2;  // lambda_j / Delta z
+            double Qr[M + 1], Qi[M + 1];
+            {
+                double rp = 1.0;
+                sfor<0, M + 1>([&](auto s) {
+                    double qr = 0.0, qi = 0.0;
+                    sfor<0, s + 1>([&](auto m2) {
+                        const double a = aT[(long)ctri(s - m2, m2) * N + jp] * rp;
+                        if constexpr (m2 % 4 == 0) qr += a;
+                        else if constexpr (m2 % 4 == 1) qi += a;
+                        else if constexpr (m2 % 4 == 2) qr -= a;
+                        else qi -= a;
+                    });
+                    Qr[s] = qr;
+                    Qi[s] = qi;
+                    rp *= ratio;
                 });
-                Qr[s] = qr;
-                Qi[s] = qi;
-                rp *= ratio;
+            }
+            double pr = 1.0, pim = 0.0;
+            sfor<1, P + 1>([&](auto nc) {
+                constexpr int n = nc;
+                const double nr = pr * ur - pim * ui, ni = pr * ui + pim * ur;
+                pr = nr;
+                pim = ni;
+                const double hr = kPairHol[n] * pr, hi = kPairHol[n] * pim;
+                sfor<0, M + 1>([&](auto s) {
+                    constexpr int p = n - s;
+                    if constexpr (p >= 1 && p <= GM) {
+                        Tr[p] += Qr[s] * hr - Qi[s] * hi;
+                        Ti[p] += Qr[s] * hi + Qi[s] * hr;
+                    }
+                });
             });
         }
-        double Tr[GM + 1], Ti[GM + 1];
-        sfor<1, GM + 1>([&](auto p) { Tr[p] = 0.0; Ti[p] = 0.0; });
-        double pr = 1.0, pim = 0.0;
-        sfor<1, P + 1>([&](auto nc) {
-            constexpr int n = nc;
-            const double nr = pr * ur - pim * ui, ni = pr * ui + pim * ur;
-            pr = nr;
-            pim = ni;
-            const double hr = kPairHol[n] * pr, hi = kPairHol[n] * pim;
-            sfor<0, M + 1>([&](auto s) {
-                constexpr int p = n - s;
-                if constexpr (p >= 1 && p <= GM) {
-                    Tr[p] += Qr[s] * hr - Qi[s] * hi;
-                    Ti[p] += Qr[s] * hi + Qi[s] * hr;
-                }
-            });
-        });
-        sfor<1, GM + 1>([&](auto p) {
-            sfor<0, p + 1>([&](auto g2) {
-                constexpr int g1 = p - g2;
-                const double v = (g2 % 4 == 0) ? Tr[p] : (g2 % 4 == 1) ? -Ti[p] : (g2 % 4 == 2) ? -Tr[p] : Ti[p];
-                acc[ctri(g1, g2)] += 2.0 * v;
-            });
-        });
     }
-    sfor<1, KG>([&](auto g) {
-        double v = acc[g];
-        v += __shfl_xor(v, 32, 64);
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 8, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 1, 64);
-        if (lane == (g & 63)) spair[(long)j * KG + g] += v;
+    // a target without far chunks (most of a dense field) leaves here
+    if (!__syncthreads_or(any)) return;
+    sfor<1, GM + 1>([&](auto p) {
+        double vr = Tr[p], vi = Ti[p];
+        for (int off = 32; off > 0; off >>= 1) {
+            vr += __shfl_xor(vr, off, 64);
+            vi += __shfl_xor(vi, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][2 * p] = vr;
+            red[wave][2 * p + 1] = vi;
+        }
+    });
+    __syncthreads();
+    if (wave != 0) return;
+    sfor<1, GM + 1>([&](auto p) {
+        double vr = red[0][2 * p], vi = red[0][2 * p + 1];
+        for (int q = 1; q < kFarWaves; ++q) {
+            vr += red[q][2 * p];
+            vi += red[q][2 * p + 1];
+        }
+        sfor<0, p + 1>([&](auto g2) {
+            constexpr int g1 = p - g2;
+            constexpr int g = ctri(g1, g2);
+            const double v = (g2 % 4 == 0) ? vr : (g2 % 4 == 1) ? -vi : (g2 % 4 == 2) ? -vr : vi;
+            if (lane == (g & 63)) spair[(long)j * KG + g] += 2.0 * v;
+        });
     });
 }
 
@@ -365,29 +407,33 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     constexpr int GM = M == 0 ? 1 : 2 * M;
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
     if (!pair_shape_valid(sh)) return hipErrorInvalidValue;
-    if (sh.kind == 1) return launch_pair_split_M<M>(T, B, cur, st);
+    if (sh.kind == 1) return B.rank ? hipErrorInvalidValue : launch_pair_split_M<M>(T, B, cur, st);
     if (sh.far && !B.far_mask) return hipErrorInvalidValue;
     const int waves = sh.split * sh.tpb;
     dim3 grid((B.N + sh.tpb - 1) / sh.tpb);
     const size_t shmem = sh.split > 1 ? sizeof(double) * (size_t)waves * KG : 0;
-    const bool use32 = f32 && !sh.f64;
+    const bool use32 = f32 && !sh.f64 && M <= kPairF32MaxOrder;
+    const double* xt = B.xs;
+    const double* lt = B.lam2[cur];
+    const double* xsrc = B.xsS;
+    const double* lsrc = B.lam2S[cur];
     if (use32 && sh.far)
-        launch_kernel((k_pair<M, float, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT32[cur], B.s_pair, B.far_mask);
+        launch_kernel((k_pair<M, float, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc, lsrc,
+                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank);
     else if (use32)
-        launch_kernel((k_pair<M, float, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT32[cur], B.s_pair, B.far_mask);
+        launch_kernel((k_pair<M, float, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc, lsrc,
+                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank);
     else if (sh.far)
-        launch_kernel((k_pair<M, double, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs, B.lam2[cur],
-                      B.alphaT[cur], B.s_pair, B.far_mask);
+        launch_kernel((k_pair<M, double, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc,
+                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank);
     else
-        launch_kernel((k_pair<M, double, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, B.xs,
-                      B.lam2[cur], B.alphaT[cur], B.s_pair, B.far_mask);
+        launch_kernel((k_pair<M, double, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc,
+                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank);
     if (sh.far) {
         // timed on its own (the caller's slot took the near kernel)
         void* tk = timing_begin(st);
-        launch_kernel((k_pair_far<M>), dim3((B.N + 3) / 4), dim3(256), 0, st, B.N, B.xs, B.lam2[cur],
-                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.s_pair);
+        launch_kernel((k_pair_far<M>), dim3(B.N), dim3(kFarThreads), 0, st, B.N, xt, lt, xsrc, lsrc,
+                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.rank, B.s_pair);
         timing_end(tk, "pair_far", st);
     }
     return hipGetLastError();

@@ -9,9 +9,9 @@
 //   X_j[a][ix] = lambda_j^{-a} h_a((x_ix - x^j_1)/lambda_j) / (pi lambda_j^2),
 //   Y_j[a][iy] = sum_{b <= M - a} M^j_{a,b} lambda_j^{-b} h_b((y_iy - x^j_2)/lambda_j).
 // k_recon_tables builds X and Y (one thread per (j, grid line), the Hermite
-// recurrence along a), k_recon_grid forms the product in 64 x 64 tiles staged
-// through LDS and writes omega once: with few vortices the kernel is bound by
-// those writes.  Vortices are taken in chunks whose tables fit the workspace;
+// recurrence along a), k_recon_grid forms the product on the matrix cores in
+// 32 x 64 tiles and writes omega once: with few vortices the kernel is bound
+// by those writes.  Vortices are taken in chunks whose tables fit the workspace;
 // later chunks add to omega.
 //
 // Non-axisymmetric enstrophy about a centre c (eq:nonaxi_enstrophy): omega at
@@ -35,9 +35,9 @@ namespace mmvm {
 namespace {
 
 constexpr double kInvPi = 0.318309886183790671537767526745;
-constexpr int kTile = 64;       // output tile edge of the grid product
-constexpr int kTileK = 16;      // inner-dimension slab staged per step
-constexpr int kGridThreads = 256;
+constexpr int kRecRows = 32, kRecCols = 64;  // output tile of one wavefront of the grid product
+constexpr int kRecWaves = 4;                 // wavefronts per workgroup
+constexpr int kRecDepth = 4;                 // k-steps per operand group in flight
 constexpr int kRingThreads = 256;
 constexpr size_t kTableBytes = (size_t)64 << 20;  // X and Y tables of one chunk of vortices
 
@@ -146,50 +146,94 @@ __global__ __launch_bounds__(256) void k_recon_tables(int M, int K, int j0, int 
 }
 
 // omega[iy][ix] (+)= sum_l Y[l][iy] X[l][ix], l over the chunk's nl = nj (M + 1)
-// rows; workgroup = 64 x 64 tile, thread = 4 x 4 outputs
-__global__ __launch_bounds__(kGridThreads) void k_recon_grid(int nl, int nx, int ny, const double* __restrict__ X,
-                                                             const double* __restrict__ Y, double* __restrict__ om,
-                                                             int accumulate)
+// rows, on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
+// A[r0 + l%16][4s + l/16] = Y[4s + l/16][iy], B[4s + l/16][c0 + l%16] = X[..][ix]
+// and receives D[r0 + l/16 + 4q][c0 + l%16] in component q).  One wavefront
+// per 32 x 64 tile (2 x 4 blocks of 16 x 16); the operands come straight from
+// the L2-resident tables as runs of 16 consecutive grid points (128-byte
+// loads), and each store writes four whole 128-byte rows of omega, once
+// (non-temporal: the grid is not read back).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64 * kRecWaves) void k_recon_grid(int nl, int nx, int ny, const double* __restrict__ X,
+                                                              const double* __restrict__ Y, double* __restrict__ om,
+                                                              int accumulate)
 {
-    __shared__ double sX[kTileK][kTile + 1], sY[kTileK][kTile + 1];
-    const int ix0 = blockIdx.x * kTile, iy0 = blockIdx.y * kTile;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double acc[4][4] = {};
-    for (int l0 = 0; l0 < nl; l0 += kTileK) {
-        for (int e = tid; e < kTileK * kTile; e += kGridThreads) {
-            const int r = e / kTile, c = e - r * kTile;
-            const int l = l0 + r;
-            sX[r][c] = (l < nl && ix0 + c < nx) ? X[(long)l * nx + ix0 + c] : 0.0;
-            sY[r][c] = (l < nl && iy0 + c < ny) ? Y[(long)l * ny + iy0 + c] : 0.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (nx + kRecCols - 1) / kRecCols;
+    const int tile = blockIdx.x * kRecWaves + wave;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    if (ty * kRecRows >= ny) return;  // uniform per wavefront; no barrier in this kernel
+    const int iy0 = ty * kRecRows, ix0 = tx * kRecCols;
+    const int li = lane & 15, lk = lane >> 4;
+    int iyA[2], ixB[4];
+    bool okA[2], okB[4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        iyA[rb] = iy0 + 16 * rb + li;
+        okA[rb] = iyA[rb] < ny;
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        ixB[cb] = ix0 + 16 * cb + li;
+        okB[cb] = ixB[cb] < nx;
+    }
+    dbl4 acc[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // operands of kRecDepth k-steps in flight: the next group is loaded while
+    // the current one multiplies (one L2 round trip per group, not per k-step)
+    const int ks = (nl + 3) >> 2;
+    double a[kRecDepth][2], b[kRecDepth][4];
+    auto load_group = [&](int s0, double (&ga)[kRecDepth][2], double (&gb)[kRecDepth][4]) {
+#pragma unroll
+        for (int d = 0; d < kRecDepth; ++d) {
+            const int l = 4 * (s0 + d) + lk;
+            const bool okl = l < nl;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) ga[d][rb] = (okl && okA[rb]) ? Y[(long)l * ny + iyA[rb]] : 0.0;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) gb[d][cb] = (okl && okB[cb]) ? X[(long)l * nx + ixB[cb]] : 0.0;
         }
-        __syncthreads();
+    };
+    load_group(0, a, b);
+    for (int s0 = 0; s0 < ks; s0 += kRecDepth) {
+        double an[kRecDepth][2], bn[kRecDepth][4];
+        if (s0 + kRecDepth < ks) load_group(s0 + kRecDepth, an, bn);
 #pragma unroll
-        for (int r = 0; r < kTileK; ++r) {
-            double xv[4], yv[4];
+        for (int d = 0; d < kRecDepth; ++d)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                xv[q] = sX[r][tx + 16 * q];
-                yv[q] = sY[r][ty + 16 * q];
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[d][rb], b[d][cb], acc[rb][cb], 0, 0, 0);
+        if (s0 + kRecDepth < ks) {
+#pragma unroll
+            for (int d = 0; d < kRecDepth; ++d) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) a[d][rb] = an[d][rb];
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) b[d][cb] = bn[d][cb];
             }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], xv[b], acc[a][b]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int iy = iy0 + ty + 16 * a;
-        if (iy >= ny) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int ix = ix0 + tx + 16 * b;
-            if (ix >= nx) continue;
-            double* o = om + (long)iy * nx + ix;
-            *o = accumulate ? *o + acc[a][b] : acc[a][b];
         }
     }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int iy = iy0 + 16 * rb + lk + 4 * q;
+            if (iy >= ny) continue;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                if (!okB[cb]) continue;
+                double* o = om + (long)iy * nx + ixB[cb];
+                const double v = acc[rb][cb][q];
+                if (accumulate) *o += v;
+                else __builtin_nontemporal_store(v, o);
+            }
+        }
 }
 
 // lambda_j(t)^2 = lambda_{j,0}^2 + 4 nu t (eq:phi00) of vortices j0 .. j0 + cnt - 1; the
@@ -344,10 +388,10 @@ mmvm_status mmvm_vorticity_grid(const mmvm_problem* prob, double t, const double
         const int tb = (int)std::min<long>((tot + 255) / 256, 8192);
         hipLaunchKernelGGL(k_recon_tables, dim3(tb), dim3(256), 0, st, M, K, j0, nj, (int)nx, (int)ny, x0, y0, h, x,
                            mom, (const double*)lam2, X, Y);
-        dim3 grid((nx + kTile - 1) / kTile, (ny + kTile - 1) / kTile);
+        const long tiles = (long)((nx + kRecCols - 1) / kRecCols) * ((ny + kRecRows - 1) / kRecRows);
         void* tk = timing_begin(st);
-        launch_kernel(k_recon_grid, grid, dim3(kGridThreads), 0, st, nj * M1, (int)nx, (int)ny, (const double*)X,
-                      (const double*)Y, omega, j0 > 0 ? 1 : 0);
+        launch_kernel(k_recon_grid, dim3((unsigned)((tiles + kRecWaves - 1) / kRecWaves)), dim3(64 * kRecWaves), 0, st,
+                      nj * M1, (int)nx, (int)ny, (const double*)X, (const double*)Y, omega, j0 > 0 ? 1 : 0);
         timing_end(tk, "recon", st);
     }
     const hipError_t e = hipGetLastError();

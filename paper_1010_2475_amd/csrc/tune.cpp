@@ -100,7 +100,7 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
     }
     std::vector<PairShape> cand;
     for (int far = far_lo; far <= far_hi; ++far)
-        for (int f64 = 0; f64 <= (f32 ? 1 : 0); ++f64)
+        for (int f64 = (f32 && T.M > kPairF32MaxOrder) ? 1 : 0; f64 <= (f32 ? 1 : 0); ++f64)
             for (int split = 1; split <= 4; split <<= 1)
                 for (int tpb = 1; tpb <= 4; tpb <<= 1) {
                     PairShape s;
@@ -111,7 +111,7 @@ PairShape pair_shape_for(const DevTables& T, const StageBufs& B, int cur, bool f
                     if (pair_shape_valid(s) && (split == 1 || B.N >= 32 * split)) cand.push_back(s);
                 }
     // the few-vortex kernel (16 lanes per pair, FP64)
-    if (B.N >= 2) {
+    if (B.N >= 2 && !B.rank) {
         PairShape s;
         s.kind = 1;
         s.groups = pair_split_groups(B.N);

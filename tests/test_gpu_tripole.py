@@ -45,7 +45,7 @@ def test_second_moments_beat_plain_gaussians(env):
     """At t = 1: relative L2 and Linf errors of the order-0 and order-2 coarse
     grids against the order-24 single particle of the same blurred initial
     vorticity, on a 256 x 256 grid over [-4, 4]^2; order 2 is the closer (the
-    paper's tab:error, about 4x there)."""
+    paper's tab:error, about 4x there), by at least a factor 2."""
     torch, mm = env
     from paper_1010_2475_amd import workloads as wl
     dev = torch.device("cuda:0")
@@ -68,4 +68,5 @@ def test_second_moments_beat_plain_gaussians(env):
         d = omega(wl.tripole_coarse(M=M)) - ref
         errs[M] = (np.sqrt((d ** 2).sum() / (ref ** 2).sum()), np.abs(d).max() / np.abs(ref).max())
     print("errors at t=1", errs, flush=True)
-    assert errs[2][0] < errs[0][0] and errs[2][1] < errs[0][1], errs
+    # measured 3.5x (L2) and 2.6x (Linf); the paper's table gives 3.7x and 4.0x at t = 1
+    assert errs[2][0] < 0.5 * errs[0][0] and errs[2][1] < 0.5 * errs[0][1], errs
