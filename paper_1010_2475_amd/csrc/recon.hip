@@ -102,19 +102,23 @@ const std::vector<double>& gauss_legendre01(int n)
     return v;
 }
 
-// X[j][a][ix] (thread per (j, ix)) and Y[j][a][iy] (thread per (j, iy)) of
-// vortices j0 .. j0 + nj - 1
+// X[j][a][ix] (thread per (j, ix)) and Y[j][a][iy] (thread per (j, iy, group of
+// kYGroup values of a: the moment sums are the bulk of the work) of vortices
+// j0 .. j0 + nj - 1
+constexpr int kYGroup = 8;
+
 __global__ __launch_bounds__(256) void k_recon_tables(int M, int K, int j0, int nj, int nx, int ny, double gx0,
                                                       double gy0, double h, const double* __restrict__ x,
                                                       const double* __restrict__ mom,
                                                       const double* __restrict__ lam2, double* __restrict__ X,
                                                       double* __restrict__ Y)
 {
-    const int M1 = M + 1;
-    const long tx = (long)nj * nx, total = tx + (long)nj * ny;
+    const int M1 = M + 1, ng = (M1 + kYGroup - 1) / kYGroup;
+    const long tx = (long)nj * nx, total = tx + (long)nj * ny * ng;
     for (long id = blockIdx.x * (long)blockDim.x + threadIdx.x; id < total; id += (long)gridDim.x * blockDim.x) {
         const bool isx = id < tx;
-        const long e = isx ? id : id - tx;
+        const long e = isx ? id : (id - tx) / ng;
+        const int grp = isx ? 0 : (int)((id - tx) - e * ng);
         const int n = isx ? nx : ny;
         const int jj = (int)(e / n), i = (int)(e - (long)jj * n), j = j0 + jj;
         const double l2 = lam2[j], il = 1.0 / sqrt(l2);
@@ -136,7 +140,8 @@ __global__ __launch_bounds__(256) void k_recon_tables(int M, int K, int j0, int 
         } else {
             const double* mj = mom + (long)j * K;
             double* o = Y + (long)jj * M1 * ny + i;
-            for (int a = 0; a <= M; ++a) {
+            const int a1 = min(M1, (grp + 1) * kYGroup);
+            for (int a = grp * kYGroup; a < a1; ++a) {
                 double s = 0.0;
                 for (int b = 0; a + b <= M; ++b) s = fma(mj[ctri(a, b)], hv[b], s);
                 o[(long)a * ny] = s;
@@ -337,13 +342,15 @@ __global__ __launch_bounds__(kRingThreads) void k_enstrophy_rings(int N, int M, 
     }
 }
 
-__global__ void k_enstrophy_sum(int nr, const double* __restrict__ ring, double* __restrict__ E)
+// E = the sum of the ring values: lane l adds rings l, l + 64, ... in order,
+// then a fixed shuffle tree (the same bits on every run)
+__global__ __launch_bounds__(64) void k_enstrophy_sum(int nr, const double* __restrict__ ring, double* __restrict__ E)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double e = 0.0;
-        for (int i = 0; i < nr; ++i) e += ring[i];
-        *E = e;
-    }
+    const int lane = threadIdx.x;
+    double e = 0.0;
+    for (int i = lane; i < nr; i += 64) e += ring[i];
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    if (lane == 0) *E = e;
 }
 
 size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -384,7 +391,7 @@ mmvm_status mmvm_vorticity_grid(const mmvm_problem* prob, double t, const double
     launch_lam2(prob, t, lam2, st);
     for (int j0 = 0; j0 < N; j0 += chunk) {
         const int nj = std::min(chunk, N - j0);
-        const long tot = (long)nj * (nx + ny);
+        const long tot = (long)nj * (nx + (long)ny * ((M1 + kYGroup - 1) / kYGroup));
         const int tb = (int)std::min<long>((tot + 255) / 256, 8192);
         hipLaunchKernelGGL(k_recon_tables, dim3(tb), dim3(256), 0, st, M, K, j0, nj, (int)nx, (int)ny, x0, y0, h, x,
                            mom, (const double*)lam2, X, Y);
