@@ -33,7 +33,7 @@ struct Workspace {
     hipStream_t cap_stream = nullptr;  // where the graph is captured
     hipGraphExec_t graph = nullptr;
     hipEvent_t graph_done = nullptr;   // recorded after the replays of a call
-    int graph_kind = -1, graph_M = -1, graph_N = -1;
+    int graph_kind = -1, graph_M = -1, graph_N = -1, graph_prec = -1;
     double graph_dt = 0.0;
     const void* graph_tables = nullptr;
     const void* graph_x = nullptr;

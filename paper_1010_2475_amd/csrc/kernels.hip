@@ -48,6 +48,17 @@ hipError_t lds_limit_once(const void* fn, size_t bytes, const char* what)
     return e;
 }
 
+// t0 + (n + c) dt as the host evaluates it, with separate roundings: HIP's
+// __dmul_rn / __dadd_rn are plain operations that -ffp-contract fuses into one
+// fused multiply-add, so contraction is switched off here
+__device__ __forceinline__ double clock_time(double t0, long long n, double c, double dt)
+{
+#pragma clang fp contract(off)
+    const double a = (double)n + c;
+    const double p = a * dt;
+    return t0 + p;
+}
+
 // ---------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------
@@ -1340,11 +1351,10 @@ __global__ __launch_bounds__(kSelfThreads) void k_self_mfma(DevTables T, StageBu
         if (tid <= M) {
             double tp = P.t_prev, tn = P.t_next;
             if (P.clock) {
-                // t0 + (n + c) dt as the host evaluates it: separate roundings, no fused multiply-add
                 const double t0 = P.clock->t0;
                 const long long n = P.clock->n;
-                tp = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_prev), P.c_prev), P.dt));
-                tn = __dadd_rn(t0, __dmul_rn(__dadd_rn((double)(n + P.n_next), P.c_next), P.dt));
+                tp = clock_time(t0, n + P.n_prev, P.c_prev, P.dt);
+                tn = clock_time(t0, n + P.n_next, P.c_next, P.dt);
             }
             const double lam2p = l0sq + 4.0 * nuj * __dadd_rn(tp, tfj);
             const double lam2n = l0sq + 4.0 * nuj * __dadd_rn(tn, tfj);
@@ -1479,6 +1489,17 @@ hipError_t launch_set_clock(DevClock* clock, double t0, long long n, hipStream_t
     return hipGetLastError();
 }
 
+__global__ void k_advance_clock(DevClock* clock, long long by)
+{
+    if (threadIdx.x == 0) clock->n += by;
+}
+
+hipError_t launch_advance_clock(DevClock* clock, long long by, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance_clock, dim3(1), dim3(64), 0, st, clock, by);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st)
 {
     launch_kernel(k_apply_final, dim3(B.N), dim3(1024), 0, st, T, B, P);
@@ -1508,8 +1529,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DevTables T, StageBufs B,
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
     double tn = S.t_next;
-    if (S.clock)  // as the host evaluates t0 + (n + c) dt: separate roundings
-        tn = __dadd_rn(S.clock->t0, __dmul_rn(__dadd_rn((double)(S.clock->n + S.n_rel), S.c_next), S.dt));
+    if (S.clock)  // graph replay: the stage time from the device clock
+        tn = clock_time(S.clock->t0, S.clock->n + S.n_rel, S.c_next, S.dt);
     const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(tn, B.toff[j]);
     double xd1 = 0.0, xd2 = 0.0;
     if (B.interact) centre_velocity(al, sp, K, lam, red, xd1, xd2);
@@ -1775,7 +1796,10 @@ __global__ __launch_bounds__(1024) void k_stage2_small(DevTables T, StageBufs B,
     }
     const double lam2 = B.lam2[S.cur][j];
     const double lam = sqrt(lam2);
-    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(S.t_next, B.toff[j]);
+    double tn = S.t_next;
+    if (S.clock)  // graph replay: the stage time from the device clock
+        tn = clock_time(S.clock->t0, S.clock->n + S.n_rel, S.c_next, S.dt);
+    const double lam2n = B.lam0sq[j] + 4.0 * B.nuv[j] * __dadd_rn(tn, B.toff[j]);
     const double* sp = B.interact ? B.s_pair + (long)j * KG : nullptr;
     __shared__ double spl[KG];
     if (B.interact && B.pair_groups > 1) {

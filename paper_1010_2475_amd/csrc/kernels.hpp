@@ -102,9 +102,11 @@ struct StageArgs {
     double* dmom;      // RHS output      [N][K]
     DevClock* clock_bump;  // graph replay: the matrix-core stage 2 advances clock.n by clock_steps
     int clock_steps;
-    // graph replay of the double-double path: when clock is set the emit
-    // kernel takes t_next = t0 + (clock.n + n_rel + c_next) dt (the step's
-    // first self kernel advances clock.n, see launch_self)
+    // graph replay of the double-double path and of interacting small orders:
+    // when clock is set the emit kernel (double-double) or the fused stage-2
+    // kernel (small orders) takes t_next = t0 + (clock.n + n_rel + c_next) dt
+    // (the double-double step's first self kernel advances clock.n, see
+    // launch_self; the small-order graph's last node does)
     const DevClock* clock;
     int n_rel;
     double c_next;
@@ -139,6 +141,9 @@ struct ApplyArgs {
 };
 // sets a stepping clock (one thread; a kernel, so it may precede graph replays)
 hipError_t launch_set_clock(DevClock* clock, double t0, long long n, hipStream_t st);
+// advances a stepping clock by `by` steps (one thread; the last node of a graph
+// whose kernels read the clock)
+hipError_t launch_advance_clock(DevClock* clock, long long by, hipStream_t st);
 bool stage2_fuses_emit(int M, bool dd, bool solo);
 hipError_t launch_self_apply(const DevTables& T, const StageBufs& B, int cur, const ApplyArgs& P, hipStream_t st);
 hipError_t launch_apply_final(const DevTables& T, const StageBufs& B, const ApplyArgs& P, hipStream_t st);

@@ -96,18 +96,43 @@ static hipError_t launch_dd_step(const DevTables& T, Workspace& W, StageArgs A, 
     return hipSuccess;
 }
 
-enum { kGraphMFMA = 0, kGraphDD = 1 };
-constexpr int kDDGraphSteps = 4;  // steps per graph of the double-double path
+// One step of interacting vortices of the small orders (pair kernels, then
+// the fused stage-2 / RK4 kernel of each stage; the stage buffers return to
+// buffer 0 after the four stages), q steps after the graph's first: the fused
+// kernel, the only one that reads a time, takes it from the device clock.  Its
+// RK4 update writes the caller's state in place.
+static hipError_t launch_small_step(const DevTables& T, Workspace& W, StageArgs A, int q, mmvm_precision prec,
+                                    hipStream_t st)
+{
+    int cur = 0;
+    for (int s = 0; s < 4; ++s) {
+        A.stage = s;
+        A.cur = cur;
+        A.clock = W.clock;
+        A.n_rel = q;
+        A.c_next = kStageC[s + 1];
+        if (run_stage_bufs(T, W.bufs, prec, A, st, nullptr) != MMVM_OK) return hipErrorUnknown;
+        cur ^= 1;
+    }
+    return hipSuccess;
+}
+
+enum { kGraphMFMA = 0, kGraphDD = 1, kGraphSmall = 2 };
+constexpr int kDDGraphSteps = 4;     // steps per graph of the double-double path
+constexpr int kSmallGraphSteps = 8;  // steps per graph of interacting small orders
 
 // The workspace's stepping graph of this kind for this (order, batch, dt, and
 // for the double-double path the caller's state), captured on first use; null
 // if capture is not possible here.
-static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const StageArgs& A, int kind, hipStream_t st)
+static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const StageArgs& A, int kind, hipStream_t st,
+                                     mmvm_precision prec = MMVM_FP64)
 {
-    const void* gx = kind == kGraphDD ? (const void*)A.x : nullptr;
-    const void* gm = kind == kGraphDD ? (const void*)A.mom : nullptr;
+    const bool own_state = kind == kGraphDD || kind == kGraphSmall;  // the graph updates the caller's state
+    const void* gx = own_state ? (const void*)A.x : nullptr;
+    const void* gm = own_state ? (const void*)A.mom : nullptr;
+    const int gp = kind == kGraphSmall ? (int)prec : -1;  // the pair kernels differ by precision
     if (W.graph && W.graph_kind == kind && W.graph_M == T.M && W.graph_N == W.bufs.N && W.graph_dt == A.dt &&
-        W.graph_tables == &T && W.graph_x == gx && W.graph_mom == gm)
+        W.graph_tables == &T && W.graph_x == gx && W.graph_mom == gm && W.graph_prec == gp)
         return W.graph;
     // an older graph may still be queued: it is retired behind the event of
     // its last replays and destroyed once that has fired
@@ -129,6 +154,10 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
     if (kind == kGraphDD) {
         e = hipSuccess;
         for (int q = 0; q < kDDGraphSteps && e == hipSuccess; ++q) e = launch_dd_step(T, W, A, cs);
+    } else if (kind == kGraphSmall) {
+        e = hipSuccess;
+        for (int q = 0; q < kSmallGraphSteps && e == hipSuccess; ++q) e = launch_small_step(T, W, A, q, prec, cs);
+        if (e == hipSuccess) e = launch_advance_clock(W.clock, kSmallGraphSteps, cs);
     } else {
         e = hipSuccess;
         for (int q = 0; q < kGraphSteps && e == hipSuccess; ++q)
@@ -150,6 +179,7 @@ static hipGraphExec_t stepping_graph(const DevTables& T, Workspace& W, const Sta
     }
     W.graph = x;
     W.graph_kind = kind;
+    W.graph_prec = gp;
     W.graph_x = gx;
     W.graph_mom = gm;
     W.graph_M = T.M;
@@ -261,7 +291,28 @@ mmvm_status run_steps(const DevTables& T, Workspace& W, double t0, double dt, in
     // the remaining steps direct
     const bool dd_graph = use_dd(T.M, prec) && !W.bufs.interact && graphs_enabled() && !timing_on() && W.clock;
     if (dd_graph && nsteps - 1 < kGraphMinSteps) (void)stepping_graph(T, W, A, kGraphDD, st);  // captured for later calls
+    // interacting vortices of the small orders: step 0 direct (it also tunes the
+    // pair kernel's shape), then replays of a kSmallGraphSteps-step graph on a
+    // clock that starts at step 1, then the remaining steps direct
+    const bool small_graph = W.bufs.interact && stage2_fuses_self(T.M, use_dd(T.M, prec), false) &&
+                             graphs_enabled() && !timing_on() && W.clock;
     for (int64_t n = 0; n < nsteps; ++n) {
+        if (n == 1 && small_graph) {
+            hipGraphExec_t g = stepping_graph(T, W, A, kGraphSmall, st, prec);
+            const int64_t reps = (nsteps - 1) / kSmallGraphSteps;
+            if (g && reps > 0) {
+                hipError_t e = launch_set_clock(W.clock, t0, 1, st);
+                for (int64_t q = 0; q < reps && e == hipSuccess; ++q) e = hipGraphLaunch(g, st);
+                if (e == hipSuccess) e = hipEventRecord(W.graph_done, st);
+                if (e != hipSuccess) {
+                    report_hip_error(e, "small-order stepping graph replay");
+                    return MMVM_EDEVICE;
+                }
+                count_graph_replays(reps);
+                n += kSmallGraphSteps * reps;  // the rest is launched directly
+                if (n >= nsteps) return MMVM_OK;
+            }
+        }
         if (n == 1 && dd_graph && nsteps - 1 >= kGraphMinSteps) {
             hipGraphExec_t g = stepping_graph(T, W, A, kGraphDD, st);
             if (g) {

@@ -362,6 +362,42 @@ def test_graph_replay_matches_direct_launches(env, M, prec, nsteps):
     assert np.array_equal(m_g2.cpu().numpy(), m_d2.cpu().numpy())
 
 
+@pytest.mark.parametrize("N,M,prec,nsteps", [(64, 6, 0, 21), (64, 4, 1, 26), (40, 2, 0, 9), (1100, 3, 1, 18)])
+def test_graph_replay_interacting_matches_direct_launches(env, N, M, prec, nsteps):
+    """Interacting vortices of the small orders replay a captured graph of
+    eight steps (pair kernels and the fused stage-2 / RK4 kernel, stage times
+    from a device clock): the same bits as direct launches, for a first call,
+    a continuing call on the same buffers (the graph is reused) and a call on
+    new buffers (recaptured).  N = 1100: sorted sources and the far split."""
+    torch, mm = env
+    w = structure_multi(N, M, 400 + N + M)
+    r0 = mm.timing_get("graph")[1]
+    X_d, m_d = _step_env(env, w, 0.02, nsteps, prec, False)
+    assert mm.timing_get("graph")[1] == r0
+    X_g, m_g = _step_env(env, w, 0.02, nsteps, prec, True)
+    assert mm.timing_get("graph")[1] == r0 + (nsteps - 1) // 8
+    assert np.array_equal(m_g.cpu().numpy(), m_d.cpu().numpy())
+    assert np.array_equal(X_g.cpu().numpy(), X_d.cpu().numpy())
+    t1 = 0.02 + nsteps * w.dt
+    _step_env(env, w, t1, nsteps + 5, prec, False, X=X_d, Mo=m_d)
+    _step_env(env, w, t1, nsteps + 5, prec, True, X=X_g, Mo=m_g)
+    assert np.array_equal(m_g.cpu().numpy(), m_d.cpu().numpy())
+    assert np.array_equal(X_g.cpu().numpy(), X_d.cpu().numpy())
+    X_d2, m_d2 = _step_env(env, w, 0.0, nsteps, prec, False)
+    X_g2, m_g2 = _step_env(env, w, 0.0, nsteps, prec, True)
+    assert np.array_equal(m_g2.cpu().numpy(), m_d2.cpu().numpy())
+    assert np.array_equal(X_g2.cpu().numpy(), X_d2.cpu().numpy())
+
+
+def structure_multi(N, M, seed):
+    """random_multi-like vortices (inside the dilute square for N >= 1024) with
+    decaying higher moments."""
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.dilute_multi(N=N, M=M, seed=seed) if N >= 1024 else wl.random_multi(N=N, M=M, seed=seed)
+    structure(w, seed + 1)
+    return w
+
+
 @pytest.mark.parametrize("M,prec", [(20, 1), (32, 0)])
 def test_graph_replay_batch_matches_direct_launches(env, M, prec):
     """A batch of three solves (own viscosities and cores) stepped through
