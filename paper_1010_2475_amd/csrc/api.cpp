@@ -271,7 +271,8 @@ Workspace::~Workspace()
 namespace {
 struct Layout {
     size_t flag, lam0, xs, ys, accx, accm, lam2[2], alpha[2], alphaT[2], alphaT32[2], alphaD[2], alphaS[2], sself,
-        sselflo, spair, ppart, fmask, rank, perm, xsS, lam2S[2], spad, ystate[2], accd, gpartd, gpart, clock, total;
+        sselflo, spair, ppart, fmask, rank, perm, xsS, lam2S[2], chunkmp, spad, ystate[2], accd, gpartd, gpart, clock,
+        total;
 };
 Layout layout_for(int N_, int M_, bool need_dd, bool solo)
 {
@@ -316,6 +317,7 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     L.perm = add(sorted ? sizeof(int) * N_ : 0);
     L.xsS = add(sorted ? sizeof(double) * 2 * N_ : 0);
     for (int q = 0; q < 2; ++q) L.lam2S[q] = add(sorted ? sizeof(double) * N_ : 0);
+    L.chunkmp = add(sorted ? sizeof(double) * (size_t)((N_ + 63) / 64) * kChunkRec : 0);
     L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
         const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;
@@ -368,6 +370,7 @@ size_t stage_layout(char* b, int N_, int M_, bool need_dd, bool solo, StageBufs*
     bufs.perm = sorted ? (const int*)(b + L.perm) : nullptr;
     bufs.xsS = sorted ? (double*)(b + L.xsS) : bufs.xs;
     for (int q = 0; q < 2; ++q) bufs.lam2S[q] = sorted ? (double*)(b + L.lam2S[q]) : bufs.lam2[q];
+    bufs.chunk_mp = sorted ? (double*)(b + L.chunkmp) : nullptr;
     bufs.s_pad = (double*)(b + L.spad);
     for (int q = 0; q < 2; ++q) bufs.ystate[q] = mx ? (double*)(b + L.ystate[q]) : nullptr;
     bufs.accD = mx ? (double*)(b + L.accd) : nullptr;

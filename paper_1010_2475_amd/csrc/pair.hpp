@@ -2,6 +2,7 @@
 // translation unit per order, so that the fully unrolled variants compile in
 // parallel).
 #pragma once
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -302,11 +303,19 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
                                                           const double* __restrict__ lam2,
                                                           const double* __restrict__ aT,
                                                           const unsigned char* __restrict__ farmask,
-                                                          const int* __restrict__ rank, double* __restrict__ spair)
+                                                          const int* __restrict__ rank,
+                                                          const double* __restrict__ cmp, double* __restrict__ spair)
 {
     constexpr int P = M == 0 ? 1 : 3 * M;
     constexpr int GM = M == 0 ? 1 : 2 * M;
     constexpr int KG = (GM + 1) * (GM + 2) / 2;
+    // a far chunk of radius r_c at distance |zeta| from the target takes its
+    // multipole expansion when r_c <= theta |zeta|: the truncation after
+    // kFarPM terms is then below ~3e-14 of the chunk's own contribution for
+    // every derivative order p <= 2M (the tail ratio of term n is about
+    // theta^n C(n + p - 1, n))
+    constexpr double kTheta2 = M >= 5 ? 0.0625 : 0.09;
+    static_assert(kFarPM + GM <= kPairHolFarMax, "hol[n] of every expansion term");
     __shared__ double red[kFarWaves][2 * GM + 2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = blockIdx.x;
     // chunk c0 + b of a group of 64 belongs to this wavefront when b = wave mod kFarWaves
@@ -329,6 +338,41 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
         while (far) {
             const int c = c0 + __builtin_ctzll(far);
             far &= far - 1;
+            if (cmp) {
+                const double* rec = cmp + (long)c * kChunkRec;
+                const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
+                const double rho2 = zr * zr + zi * zi;
+                if (rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
+                    if (lane <= kFarPM) {
+                        // lane n: T_p += B_n hol[n + p] lambda_j^p zeta^{-(n + p)}, p = 1 .. 2M
+                        const double br = rec[4 + 2 * lane], bi = rec[5 + 2 * lane];
+                        const double id = 1.0 / rho2;
+                        const double z1r = zr * id, z1i = -zi * id;  // 1 / zeta
+                        double wr = 1.0, wi = 0.0, qr = z1r, qi = z1i;
+                        for (int e = lane + 1; e; e >>= 1) {  // zeta^{-(n + 1)}
+                            if (e & 1) {
+                                const double t = wr * qr - wi * qi;
+                                wi = wr * qi + wi * qr;
+                                wr = t;
+                            }
+                            const double t = qr * qr - qi * qi;
+                            qi = 2.0 * qr * qi;
+                            qr = t;
+                        }
+                        double vr = kPairHolFar[lane + 1] * lj * wr, vi = kPairHolFar[lane + 1] * lj * wi;
+                        const double ur = lj * z1r, ui = lj * z1i;  // lambda_j / zeta
+                        sfor<1, GM + 1>([&](auto p) {
+                            Tr[p] += br * vr - bi * vi;
+                            Ti[p] += br * vi + bi * vr;
+                            const double f = -(double)(lane + p);  // hol[m + 1] / hol[m] = -m
+                            const double nr = (vr * ur - vi * ui) * f, ni = (vr * ui + vi * ur) * f;
+                            vr = nr;
+                            vi = ni;
+                        });
+                    }
+                    continue;
+                }
+            }
             const int jp = c * 64 + lane;
             if (jp >= N || jp == self) continue;
             const double lp2 = lam2[jp];
@@ -401,6 +445,94 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
     });
 }
 
+// Multipole expansion of each chunk of 64 sorted sources about its centre z_c
+// (the mean of its positions).  Beyond the cores the field of source q is
+// sum_s Qu_s L^(s)(z - z_q), L^(s) the s-th complex derivative of the
+// harmonic potential (L^(n)(z) = hol[n] / z^n), Qu_s = sum_{|m| = s} M_m i^{m2}
+// its unscaled multipoles; the Taylor series of L^(s) about z - z_c gives the
+// chunk's field as sum_n B_n L^(n)(z - z_c),
+//   B_n = sum_q sum_{s <= min(n, M)} Qu_{q,s} (-d_q)^{n-s} / (n-s)!,  d_q = z_q - z_c,
+// convergent for |z - z_c| > max |d_q| (the chunk radius), kept to n = kFarPM.
+// One wavefront per chunk, lane = source; every sum over the chunk is a
+// wavefront shuffle tree (fixed order).
+template <int M>
+__global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* __restrict__ xs,
+                                                          const double* __restrict__ lam2,
+                                                          const double* __restrict__ aT, double* __restrict__ cmp)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), nch = (N + 63) >> 6;
+    if (c >= nch) return;  // uniform per wavefront; no barrier in this kernel
+    const int q = c * 64 + lane;
+    const bool live = q < N;
+    const double x1 = live ? xs[2 * q] : 0.0, x2 = live ? xs[2 * q + 1] : 0.0;
+    double s1 = x1, s2 = x2, cnt = live ? 1.0 : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off, 64);
+        s2 += __shfl_xor(s2, off, 64);
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const double c1 = s1 / cnt, c2 = s2 / cnt;
+    const double d1 = live ? x1 - c1 : 0.0, d2 = live ? x2 - c2 : 0.0;
+    double r2 = d1 * d1 + d2 * d2;
+    for (int off = 32; off > 0; off >>= 1) r2 = fmax(r2, __shfl_xor(r2, off, 64));
+    double qr[M + 1], qi[M + 1];
+    sfor<0, M + 1>([&](auto s) { qr[s] = 0.0; qi[s] = 0.0; });
+    if (live) {
+        const double lq = sqrt(lam2[q]);
+        double lp = 1.0;  // lambda_q^s: the unscaled moments M = alpha lambda^{|m|}
+        sfor<0, M + 1>([&](auto s) {
+            sfor<0, s + 1>([&](auto m2) {
+                const double a = aT[(long)ctri(s - m2, m2) * N + q] * lp;
+                if constexpr (m2 % 4 == 0) qr[s] += a;
+                else if constexpr (m2 % 4 == 1) qi[s] += a;
+                else if constexpr (m2 % 4 == 2) qr[s] -= a;
+                else qi[s] -= a;
+            });
+            lp *= lq;
+        });
+    }
+    double* rec = cmp + (long)c * kChunkRec;
+    if (lane == 0) {
+        rec[0] = c1;
+        rec[1] = c2;
+        rec[2] = sqrt(r2);
+        rec[3] = 0.0;
+    }
+    // e_k = (-d)^k / k!: er[s], ei[s] hold e_{n - s} (zero for n - s < 0)
+    double er[M + 1], ei[M + 1];
+    sfor<0, M + 1>([&](auto s) { er[s] = 0.0; ei[s] = 0.0; });
+    double pr = 1.0, pim = 0.0;  // e_n
+    for (int n = 0; n <= kFarPM; ++n) {
+        if (n > 0) {
+            const double f = 1.0 / (double)n;
+            const double nr = -(pr * d1 - pim * d2) * f, ni = -(pr * d2 + pim * d1) * f;
+            pr = nr;
+            pim = ni;
+        }
+        sfor<0, M>([&](auto t) {
+            constexpr int s = M - t;  // M .. 1
+            er[s] = er[s - 1];
+            ei[s] = ei[s - 1];
+        });
+        er[0] = pr;
+        ei[0] = pim;
+        double br = 0.0, bi = 0.0;
+        sfor<0, M + 1>([&](auto s) {
+            br += qr[s] * er[s] - qi[s] * ei[s];
+            bi += qr[s] * ei[s] + qi[s] * er[s];
+        });
+        for (int off = 32; off > 0; off >>= 1) {
+            br += __shfl_xor(br, off, 64);
+            bi += __shfl_xor(bi, off, 64);
+        }
+        if (lane == (n & 63)) {
+            rec[4 + 2 * n] = br;
+            rec[5 + 2 * n] = bi;
+        }
+    }
+}
+
 template <int M>
 hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
@@ -430,10 +562,22 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
         launch_kernel((k_pair<M, double, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc,
                       lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank);
     if (sh.far) {
+        // chunk expansions (sorted sources only: unsorted chunks are not compact);
+        // MMVM_FAR_M2P=0 keeps every far pair on the pair-by-pair form
+        const char* env = std::getenv("MMVM_FAR_M2P");
+        const bool m2p = !(env && env[0] == '0');
+        const double* cmp = (m2p && B.rank && B.chunk_mp) ? B.chunk_mp : nullptr;
+        if (cmp) {
+            const int nch = (B.N + 63) >> 6;
+            void* tk = timing_begin(st);
+            launch_kernel((k_chunk_multipoles<M>), dim3((nch + 3) / 4), dim3(256), 0, st, B.N, xsrc, lsrc,
+                          (const double*)B.alphaT[cur], B.chunk_mp);
+            timing_end(tk, "pair_mp", st);
+        }
         // timed on its own (the caller's slot took the near kernel)
         void* tk = timing_begin(st);
         launch_kernel((k_pair_far<M>), dim3(B.N), dim3(kFarThreads), 0, st, B.N, xt, lt, xsrc, lsrc,
-                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.rank, B.s_pair);
+                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.rank, cmp, B.s_pair);
         timing_end(tk, "pair_far", st);
     }
     return hipGetLastError();

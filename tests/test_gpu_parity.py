@@ -772,3 +772,34 @@ def test_mixed_bound_from_decaying_to_flat_spectra(env, orc, N, M, decay, amp):
     print("mixed N=%d M=%d decay=%g amp=%g: dM %.2e dx %.2e" % (N, M, decay, amp, err, errx), flush=True)
     bar = MIXED_TOL if decay > 0 else 2 * MIXED_TOL
     assert err <= bar and errx <= MIXED_TOL
+
+
+@pytest.mark.parametrize("N,M", [(4096, 4), (3000, 6), (2048, 2)])
+def test_far_field_chunk_expansions_match_pairwise(env, orc, N, M):
+    """Far chunks that lie well away from a target (radius <= 0.3 of the
+    distance at orders <= 4, 0.25 above) enter through the multipole expansion
+    of the whole chunk (40 terms) instead of pair by pair: the right-hand side
+    equals the pairwise far field (MMVM_FAR_M2P=0) to rounding and the oracle's
+    sampled rows to the FP64 bar, and the two differ (the expansions are used)."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.dilute_multi(N=N, M=M, seed=70 + M)
+    structure(w, 71 + M)
+    t = 0.1
+    os.environ["MMVM_FAR_M2P"] = "0"
+    try:
+        dx_p, dm_p = gpu_rhs(env, w, t, 0)
+    finally:
+        os.environ.pop("MMVM_FAR_M2P", None)
+    dx_e, dm_e = gpu_rhs(env, w, t, 0)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    assert not np.array_equal(dm_e, dm_p)
+    assert normwise(M, lam_t, dm_p, dm_e, w.mom[:, 0], dx_p) <= 1e-13
+    assert np.abs(dx_e - dx_p).max() <= 1e-13 * np.abs(dx_p).max()
+    js = [0, N // 3, N - 1]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, dxr = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    dx_r = dxr.reshape(3, w.K, 2)[:, 0, :]
+    assert normwise(M, lam_t[js], d.reshape(3, w.K), dm_e[js], w.mom[js, 0], dx_r) <= FP64_TOL
+    assert np.abs(dx_e[js] - dx_r).max() <= FP64_TOL * np.abs(dx_r).max()
