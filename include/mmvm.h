@@ -167,7 +167,9 @@ mmvm_status mmvm_sync(void* stream);
  * mom0[n][K], prob->lambda0) and returns at once with a ticket; requests are
  * admitted when a slot and their HBM footprint are free, run together with the
  * other resident requests step by step, and leave at completion.  Thread-safe.
- * The result of a request does not depend on what else is resident. */
+ * The result of a request does not depend on what else is resident.
+ * Requests are stepped on 4 HIP streams (the environment variable
+ * MMVM_SERVER_STREAMS, 1-16, read at mmvm_server_create, changes that). */
 typedef struct mmvm_server mmvm_server;
 typedef struct {
     double t_arrive, t_admit, t_start, t_done; /* seconds, server clock */

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -38,7 +39,8 @@
 namespace mmvm {
 namespace {
 
-constexpr int kStreams = 4;          // hardware queues per process on the target
+constexpr int kStreams = 4;          // default streams: HIP's default hardware queues per process
+constexpr int kMaxStreams = 16;       // MMVM_SERVER_STREAMS may ask for up to this many
 constexpr int64_t kChunkSteps = 25;  // RK4 steps per scheduling quantum
 constexpr int kMaxBypass = 64;       // admissions that may pass a waiting head
 
@@ -130,7 +132,8 @@ struct mmvm_server {
     int max_slots = 0;
     int device = 0;
     std::chrono::steady_clock::time_point t_origin;
-    hipStream_t streams[kStreams] = {};
+    hipStream_t streams[kMaxStreams] = {};
+    int nstreams = kStreams;
 
     std::mutex mu;                    // guards the fields below up to `stop`
     std::condition_variable cv_work;  // worker wake-up
@@ -205,7 +208,7 @@ Slot* mmvm_server::acquire_slot(size_t dev_doubles, size_t host_doubles, mmvm_st
 mmvm_status mmvm_server::start_request(Request* r)
 {
     r->stream = next_stream;
-    next_stream = (next_stream + 1) % kStreams;
+    next_stream = (next_stream + 1) % nstreams;
     mmvm_status s = MMVM_OK;
     const size_t nd = state_doubles(r->n, r->order);
     r->slot = acquire_slot(nd, nd, &s);
@@ -452,7 +455,7 @@ void mmvm_server::run()
                     g.members = bl.second;
                     g.steps = bl.first;
                     g.stream = next_stream;
-                    next_stream = (next_stream + 1) % kStreams;
+                    next_stream = (next_stream + 1) % nstreams;
                     mmvm_status s = MMVM_OK;
                     const size_t nd = state_doubles((int)g.members.size(), std::get<0>(g.key));
                     g.slot = acquire_slot(nd, 0, &s);
@@ -489,7 +492,11 @@ mmvm_status mmvm_server_create(size_t hbm_budget_bytes, int32_t max_slots, mmvm_
     s->max_slots = max_slots;
     s->t_origin = std::chrono::steady_clock::now();
     if (hipGetDevice(&s->device) != hipSuccess) return MMVM_EDEVICE;
-    for (int i = 0; i < kStreams; ++i)
+    if (const char* e = std::getenv("MMVM_SERVER_STREAMS")) {
+        const int n = std::atoi(e);
+        if (n >= 1 && n <= kMaxStreams) s->nstreams = n;
+    }
+    for (int i = 0; i < s->nstreams; ++i)
         if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) return MMVM_EDEVICE;
     mmvm_server* raw = s.release();
     raw->worker = std::thread([raw] { raw->run(); });
@@ -574,10 +581,10 @@ mmvm_status mmvm_server_destroy(mmvm_server* srv)
         srv->cv_work.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    for (int i = 0; i < kStreams; ++i)
+    for (int i = 0; i < kMaxStreams; ++i)
         if (srv->streams[i]) (void)hipStreamSynchronize(srv->streams[i]);
     srv->pool.clear();
-    for (int i = 0; i < kStreams; ++i)
+    for (int i = 0; i < kMaxStreams; ++i)
         if (srv->streams[i]) (void)hipStreamDestroy(srv->streams[i]);
     delete srv;
     return MMVM_OK;
