@@ -453,16 +453,23 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
 // chunk's field as sum_n B_n L^(n)(z - z_c),
 //   B_n = sum_q sum_{s <= min(n, M)} Qu_{q,s} (-d_q)^{n-s} / (n-s)!,  d_q = z_q - z_c,
 // convergent for |z - z_c| > max |d_q| (the chunk radius), kept to n = kFarPM.
-// One wavefront per chunk, lane = source; every sum over the chunk is a
-// wavefront shuffle tree (fixed order).
+// One workgroup per chunk, lane = source.  Every wavefront forms the centre
+// (the same shuffle trees, so the same bits), its sources' multipoles and the
+// factors (-d)^m / m! by their recurrence; wavefront w keeps the per-source
+// terms of B_n for its quarter of the n range, in LDS.  Thread t then adds
+// column t (a real or imaginary part of one B_n) over the 64 sources: four
+// interleaved partial sums in source order, combined pairwise.
+constexpr int kMpTerms = kFarPM + 1;
+constexpr int kMpPerWave = (kMpTerms + 3) / 4;
+static_assert(2 * kMpTerms <= 256, "a thread per column of the chunk sums");
+
 template <int M>
 __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* __restrict__ xs,
                                                           const double* __restrict__ lam2,
                                                           const double* __restrict__ aT, double* __restrict__ cmp)
 {
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), nch = (N + 63) >> 6;
-    if (c >= nch) return;  // uniform per wavefront; no barrier in this kernel
+    __shared__ double part[2 * kMpTerms][65];  // [column][source]; odd row length spreads the banks
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = blockIdx.x;
     const int q = c * 64 + lane;
     const bool live = q < N;
     const double x1 = live ? xs[2 * q] : 0.0, x2 = live ? xs[2 * q + 1] : 0.0;
@@ -493,17 +500,18 @@ __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* _
         });
     }
     double* rec = cmp + (long)c * kChunkRec;
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         rec[0] = c1;
         rec[1] = c2;
         rec[2] = sqrt(r2);
         rec[3] = 0.0;
     }
     // e_k = (-d)^k / k!: er[s], ei[s] hold e_{n - s} (zero for n - s < 0)
+    const int n0 = wave * kMpPerWave, n1 = n0 + kMpPerWave < kMpTerms ? n0 + kMpPerWave : kMpTerms;
     double er[M + 1], ei[M + 1];
     sfor<0, M + 1>([&](auto s) { er[s] = 0.0; ei[s] = 0.0; });
     double pr = 1.0, pim = 0.0;  // e_n
-    for (int n = 0; n <= kFarPM; ++n) {
+    for (int n = 0; n < n1; ++n) {  // uniform per wavefront
         if (n > 0) {
             const double f = 1.0 / (double)n;
             const double nr = -(pr * d1 - pim * d2) * f, ni = -(pr * d2 + pim * d1) * f;
@@ -517,19 +525,28 @@ __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* _
         });
         er[0] = pr;
         ei[0] = pim;
-        double br = 0.0, bi = 0.0;
-        sfor<0, M + 1>([&](auto s) {
-            br += qr[s] * er[s] - qi[s] * ei[s];
-            bi += qr[s] * ei[s] + qi[s] * er[s];
-        });
-        for (int off = 32; off > 0; off >>= 1) {
-            br += __shfl_xor(br, off, 64);
-            bi += __shfl_xor(bi, off, 64);
+        if (n >= n0) {
+            double br = 0.0, bi = 0.0;
+            sfor<0, M + 1>([&](auto s) {
+                br += qr[s] * er[s] - qi[s] * ei[s];
+                bi += qr[s] * ei[s] + qi[s] * er[s];
+            });
+            part[2 * n][lane] = br;
+            part[2 * n + 1][lane] = bi;
         }
-        if (lane == (n & 63)) {
-            rec[4 + 2 * n] = br;
-            rec[5 + 2 * n] = bi;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < 2 * kMpTerms) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 64; k += 4) {
+            a[0] += part[t][k];
+            a[1] += part[t][k + 1];
+            a[2] += part[t][k + 2];
+            a[3] += part[t][k + 3];
         }
+        rec[4 + t] = (a[0] + a[1]) + (a[2] + a[3]);
     }
 }
 
@@ -570,7 +587,7 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
         if (cmp) {
             const int nch = (B.N + 63) >> 6;
             void* tk = timing_begin(st);
-            launch_kernel((k_chunk_multipoles<M>), dim3((nch + 3) / 4), dim3(256), 0, st, B.N, xsrc, lsrc,
+            launch_kernel((k_chunk_multipoles<M>), dim3(nch), dim3(256), 0, st, B.N, xsrc, lsrc,
                           (const double*)B.alphaT[cur], B.chunk_mp);
             timing_end(tk, "pair_mp", st);
         }
