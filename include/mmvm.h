@@ -211,14 +211,16 @@ mmvm_status mmvm_timing_get(const char* kernel, double* total_ms, int64_t* launc
  * chunks lying wholly in a target's far field (beyond the Gaussian cores: the
  * pair field is then the harmonic multipole of the source) go to the cheaper
  * far-field kernel.  From 1024 vortices (orders 0-6) the sources of each call
- * are sorted in space (Morton order of the call's initial positions) and
+ * are sorted in space (Hilbert order of the call's initial positions) and
  * every candidate uses the far-field split, which decides per chunk at run
  * time; the environment variable MMVM_PAIR_FAR=0 (or 1) restricts the
  * candidates to shapes without (with) it.  With sorted sources a far chunk
  * whose radius is small against its distance from the target enters through
  * the chunk's 41-term multipole expansion about its centre (truncation below
- * ~3e-14 of that chunk's contribution); MMVM_FAR_M2P=0 keeps every far pair on
- * the pairwise form.  On by default (the environment
+ * ~3e-14 of that chunk's contribution), and a cell of four consecutive chunks
+ * that are all far through one expansion translated from theirs where that
+ * converges as well; MMVM_FAR_CELLS=0 keeps the chunk expansions only, and
+ * MMVM_FAR_M2P=0 every far pair on the pairwise form.  On by default (the environment
  * variable MMVM_AUTOTUNE=0 starts a process with it off).  The first launch
  * for a new key (order, precision, vortex count rounded up to a power of two)
  * times every candidate shape on the caller's stream with the caller's

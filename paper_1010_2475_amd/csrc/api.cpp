@@ -317,7 +317,7 @@ Layout layout_for(int N_, int M_, bool need_dd, bool solo)
     L.perm = add(sorted ? sizeof(int) * N_ : 0);
     L.xsS = add(sorted ? sizeof(double) * 2 * N_ : 0);
     for (int q = 0; q < 2; ++q) L.lam2S[q] = add(sorted ? sizeof(double) * N_ : 0);
-    L.chunkmp = add(sorted ? sizeof(double) * (size_t)((N_ + 63) / 64) * kChunkRec : 0);
+    L.chunkmp = add(sorted ? sizeof(double) * (size_t)far_records(N_) * kChunkRec : 0);
     L.spad = add(stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).spad() : 0);
     {
         const size_t dense = stage2_uses_mfma(M_, false, solo) ? sizeof(double) * (size_t)N_ * S2Shape(M_, 0).LP * S2Shape(M_, 0).LP : 0;

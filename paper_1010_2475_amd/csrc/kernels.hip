@@ -104,22 +104,42 @@ __global__ __launch_bounds__(256) void k_alpha_dense_clear(StageBufs B, int M)
 }
 
 // Spatial order of the pair kernels' sources: the vortices of one call
-// sorted by the Morton code of their positions at the call's start, so that
-// consecutive chunks of 64 sources are compact (a target's near chunks are
-// few, its far chunks are skipped as wholes).  One workgroup: bounding box of
-// the finite positions, 16-bit grid coordinates interleaved into a 32-bit
-// code, the vortex index below it (unique keys: a deterministic order),
-// bitonic sort of NP (a power of two >= N) keys in LDS.  Positions move within
-// a call; the order only has to stay good, not exact.
+// sorted along a Hilbert curve through their positions at the call's start, so
+// that consecutive chunks of 64 sources are compact (a target's near chunks are
+// few, its far chunks are skipped as wholes, and the expansions of chunks and
+// cells converge close to them).  A Morton (Z) order jumps across quadrant
+// edges, so chunks straddling a jump span two distant clumps: on a uniform
+// field the Hilbert order halves the mean chunk radius.  One workgroup:
+// bounding box of the finite positions, one scale for both axes onto a 16-bit
+// grid, the curve index (32 bits) with the vortex index below it (unique keys:
+// a deterministic order), bitonic sort of NP (a power of two >= N) keys in
+// LDS.  Positions move within a call; the order only has to stay good, not
+// exact.
 constexpr int kSortThreads = 1024;
 
-__device__ __forceinline__ unsigned spread_bits16(unsigned v)
+// Index of grid point (q1, q2) along the Hilbert curve of the 2^16 x 2^16 grid,
+// by the curve's recursive construction read from the top level down: at each
+// level the quadrant holding the point contributes (its rank along the curve)
+// x (points per quadrant), and the point is mapped into the frame in which that
+// quadrant's sub-curve has the standard orientation (a transpose, preceded by
+// a reflection in the last quadrant of the bottom row).
+__device__ __forceinline__ unsigned hilbert_index16(unsigned q1, unsigned q2)
 {
-    v = (v | (v << 8)) & 0x00FF00FFu;
-    v = (v | (v << 4)) & 0x0F0F0F0Fu;
-    v = (v | (v << 2)) & 0x33333333u;
-    v = (v | (v << 1)) & 0x55555555u;
-    return v;
+    unsigned d = 0;
+    for (unsigned s = 1u << 15; s > 0; s >>= 1) {
+        const unsigned r1 = (q1 & s) ? 1u : 0u, r2 = (q2 & s) ? 1u : 0u;
+        d += s * s * ((3u * r1) ^ r2);
+        if (r2 == 0) {
+            if (r1 == 1) {
+                q1 = 0xFFFFu - q1;
+                q2 = 0xFFFFu - q2;
+            }
+            const unsigned t = q1;
+            q1 = q2;
+            q2 = t;
+        }
+    }
+    return d;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_sources(int N, int NP, const double* __restrict__ x,
@@ -161,18 +181,19 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_sources(int N, int NP, co
         lo2 = fmin(lo2, red[2][w]);
         hi2 = fmax(hi2, red[3][w]);
     }
-    const double sc1 = hi1 > lo1 ? 65535.0 / (hi1 - lo1) : 0.0;
-    const double sc2 = hi2 > lo2 ? 65535.0 / (hi2 - lo2) : 0.0;
+    // one scale for both axes: grid cells are squares (compact chunks on elongated fields too)
+    const double span = fmax(hi1 - lo1, hi2 - lo2);
+    const double sc = span > 0.0 ? 65535.0 / span : 0.0;
     for (int p = tid; p < NP; p += kSortThreads) {
         unsigned long long key = ~0ull;
         if (p < N) {
             const double a = x[2 * p], b = x[2 * p + 1];
             unsigned q1 = 0, q2 = 0;
             if (isfinite(a) && isfinite(b)) {
-                q1 = (unsigned)fmin(65535.0, fmax(0.0, (a - lo1) * sc1));
-                q2 = (unsigned)fmin(65535.0, fmax(0.0, (b - lo2) * sc2));
+                q1 = (unsigned)fmin(65535.0, fmax(0.0, (a - lo1) * sc));
+                q2 = (unsigned)fmin(65535.0, fmax(0.0, (b - lo2) * sc));
             }
-            const unsigned code = spread_bits16(q1) | (spread_bits16(q2) << 1);
+            const unsigned code = hilbert_index16(q1, q2);
             key = ((unsigned long long)code << 32) | (unsigned)p;
         }
         skey[p] = key;

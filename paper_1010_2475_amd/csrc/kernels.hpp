@@ -67,7 +67,7 @@ struct StageBufs {
     double* xsS;           // [N][2] stage positions of the sources (= xs when not sorted)
     double* lam2S[2];      // [N] lambda^2 of the sources (= lam2 when not sorted)
     // alphaT / alphaT32 hold the sources in the same order
-    double* chunk_mp;      // [ceil(N / 64)][kChunkRec] multipole expansions of the sorted source chunks (or null)
+    double* chunk_mp;      // [far_records(N)][kChunkRec] multipole expansions of the sorted source chunks, then of their cells (or null)
     double* s_pad;         // [N][2][KA][RP] self table of each parity by columns g2, rows r, zero-padded (matrix-core path)
     double* alphaD[2];     // [N][LP + 16][LP] alpha[m1][m2] dense, zero beyond the triangle (matrix-core path)
     double* alphaS[2];     // [N][LP][LP] (-1)^{|l|} alpha[l1][l2] stored at (l2, l1), zero beyond the triangle
@@ -178,6 +178,15 @@ constexpr int kPairFarAlwaysN = 1024;
 // chunk = centre (2), radius, pad, then the complex coefficients B_n
 constexpr int kFarPM = 40;
 constexpr int kChunkRec = 4 + 2 * (kFarPM + 1);
+// Cells of kFarCellChunks consecutive chunks carry an expansion of their own
+// (translated from their chunks'), taken for targets far from the whole cell;
+// their records follow the chunk records
+constexpr int kFarCellChunks = 4;
+// chunk and cell records of N sorted sources
+constexpr int far_records(int N)
+{
+    return ((N + 63) >> 6) + (((N + 63) >> 6) + kFarCellChunks - 1) / kFarCellChunks;
+}
 // bytes of one target's row of the far-chunk mask (chunks of 64 sources, rows
 // padded to 8 bytes for 64-bit loads)
 constexpr int pair_mask_stride(int N) { return (((N + 63) >> 6) + 7) & ~7; }

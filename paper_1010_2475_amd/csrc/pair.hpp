@@ -63,6 +63,8 @@ constexpr double pair_inv_factorial(int P)
 // quad-precision H^B at P = 3..18), and Psi'(a) = 2 Re(i^{a2} H_{|a|}),
 // H_n = hol[n] (tau / z)^n, the harmonic part alone.
 constexpr double pair_far_w(int P) { return 50.0 + 2.5 * P; }
+// relative margin of the record-based far test against rounding at the threshold
+constexpr double kFarBoundMargin = 1.0 + 1e-9;
 
 // FAR: a wavefront whose pairs of one 64-source chunk are all beyond the
 // threshold skips them and marks the chunk in farmask[j][chunk] (0 otherwise);
@@ -77,7 +79,8 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
                                                           const double* __restrict__ lam2, const R* __restrict__ aT,
                                                           double* __restrict__ spair,
                                                           unsigned char* __restrict__ farmask,
-                                                          const int* __restrict__ rank)
+                                                          const int* __restrict__ rank,
+                                                          const double* __restrict__ crec)
 {
     constexpr int K = (M + 1) * (M + 2) / 2;
     constexpr int P = M == 0 ? 1 : 3 * M;
@@ -111,17 +114,53 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     if constexpr (F32) sfor<0, KG>([&](auto g) { acc32[g] = 0.0f; });
     int pending = 0;
 
+    const int nch = (N + 63) >> 6;
+    unsigned long long bfar = 0;  // chunks bbase .. bbase + 63 provably far (FAR with records)
+    int bbase = -64;
     for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split) {
-        if (jp == self) continue;
+        const bool own = jp == self;
+        if constexpr (!FAR) {
+            if (own) continue;
+        }
+        if constexpr (FAR) {
+            // a chunk whose record (centre, radius r_c, largest lambda^2) puts
+            // every source beyond the threshold is far without reading its
+            // sources: |x_j - x_q| >= rho - r_c, so w_q >= (rho - r_c)^2 /
+            // (lambda_j^2 + max lambda^2).  The records of 64 chunks at a time,
+            // one per lane; the other chunks take the exact test below (the
+            // same mask either way, up to a margin of rounding)
+            if (crec) {
+                const int c = jp >> 6;  // uniform: the lanes hold one chunk
+                if (c >= bbase + 64) {
+                    bbase = c & ~63;
+                    bool bf = false;
+                    const int cc = bbase + lane;
+                    if (cc < nch) {
+                        const double* r = crec + (long)cc * kChunkRec;
+                        const double e1 = xj1 - r[0], e2 = xj2 - r[1];
+                        const double gap = sqrt(e1 * e1 + e2 * e2) - r[2];
+                        bf = gap > 0.0 && gap * gap > kFarBoundMargin * pair_far_w(P) * (lj2 + r[3]);
+                    }
+                    bfar = __ballot(bf);
+                }
+                if ((bfar >> (c - bbase)) & 1ull) {
+                    if (jp == c * 64) farmask[(long)j * pair_mask_stride(N) + c] = 1;
+                    continue;
+                }
+            }
+        }
         const double lp2 = lam2[jp];
         const double c = lj2 + lp2;
         const double isc = 1.0 / sqrt(c);
         const double s1 = (xj1 - xs[2 * jp]) * isc, s2 = (xj2 - xs[2 * jp + 1]) * isc;
         const double w = s1 * s1 + s2 * s2;
         if constexpr (FAR) {
-            const bool all_far = __all(w > pair_far_w(P));  // uniform over the wavefront's active lanes
+            // every lane of the chunk takes part (the mask byte of each visited
+            // chunk is rewritten each stage); the target's own source does not
+            // count, and a chunk holding nothing else is near
+            const bool all_far = __all(own || w > pair_far_w(P)) && __any(!own);  // uniform over the wavefront
             farmask[(long)j * pair_mask_stride(N) + (jp >> 6)] = all_far ? 1 : 0;
-            if (all_far) continue;
+            if (all_far || own) continue;
         }
         const double e1 = exp(-s1 * s1), e2 = exp(-s2 * s2);
         const double E = e1 * e2;
@@ -304,7 +343,8 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
                                                           const double* __restrict__ aT,
                                                           const unsigned char* __restrict__ farmask,
                                                           const int* __restrict__ rank,
-                                                          const double* __restrict__ cmp, double* __restrict__ spair)
+                                                          const double* __restrict__ cmp,
+                                                          const double* __restrict__ cells, double* __restrict__ spair)
 {
     constexpr int P = M == 0 ? 1 : 3 * M;
     constexpr int GM = M == 0 ? 1 : 2 * M;
@@ -318,7 +358,9 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
     static_assert(kFarPM + GM <= kPairHolFarMax, "hol[n] of every expansion term");
     __shared__ double red[kFarWaves][2 * GM + 2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = blockIdx.x;
-    // chunk c0 + b of a group of 64 belongs to this wavefront when b = wave mod kFarWaves
+    // chunk c0 + b of a group of 64 belongs to this wavefront when b = wave mod
+    // kFarWaves, cell k (chunks k kFarCellChunks ...) when k = wave mod kFarWaves
+    static_assert(64 % kFarCellChunks == 0, "cells tile a group of 64 chunks");
     unsigned long long mine = 0;
     for (int b = wave; b < 64; b += kFarWaves) mine |= 1ull << b;
     const int stride = pair_mask_stride(N), nch = (N + 63) >> 6;
@@ -330,11 +372,67 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
     // entries g once, after the wavefront sum)
     double Tr[GM + 1], Ti[GM + 1];
     sfor<1, GM + 1>([&](auto p) { Tr[p] = 0.0; Ti[p] = 0.0; });
+    // an expansion record (chunk or cell) at zeta = z_j - z_c, rho2 = |zeta|^2:
+    // lane n adds T_p += B_n hol[n + p] lambda_j^p zeta^{-(n + p)}, p = 1 .. 2M
+    auto m2p = [&](const double* rec, double zr, double zi, double rho2) {
+        if (lane > kFarPM) return;
+        const double br = rec[4 + 2 * lane], bi = rec[5 + 2 * lane];
+        const double id = 1.0 / rho2;
+        const double z1r = zr * id, z1i = -zi * id;  // 1 / zeta
+        double wr = 1.0, wi = 0.0, qr = z1r, qi = z1i;
+        for (int e = lane + 1; e; e >>= 1) {  // zeta^{-(n + 1)}
+            if (e & 1) {
+                const double t = wr * qr - wi * qi;
+                wi = wr * qi + wi * qr;
+                wr = t;
+            }
+            const double t = qr * qr - qi * qi;
+            qi = 2.0 * qr * qi;
+            qr = t;
+        }
+        double vr = kPairHolFar[lane + 1] * lj * wr, vi = kPairHolFar[lane + 1] * lj * wi;
+        const double ur = lj * z1r, ui = lj * z1i;  // lambda_j / zeta
+        sfor<1, GM + 1>([&](auto p) {
+            Tr[p] += br * vr - bi * vi;
+            Ti[p] += br * vi + bi * vr;
+            const double f = -(double)(lane + p);  // hol[m + 1] / hol[m] = -m
+            const double nr = (vr * ur - vi * ui) * f, ni = (vr * ui + vi * ur) * f;
+            vr = nr;
+            vi = ni;
+        });
+    };
     int any = 0;  // this wavefront had far chunks
     for (int c0 = 0; c0 < nch; c0 += 64) {
         const bool flag = c0 + lane < nch && row[c0 + lane] != 0;
-        unsigned long long far = __ballot(flag) & mine;  // uniform per wavefront
-        any |= far != 0;
+        unsigned long long far = __ballot(flag);  // uniform per wavefront
+        any |= (far & mine) != 0;
+        if (cells) {
+            // a cell whose chunks are all far takes its own expansion where that
+            // converges (one record for kFarCellChunks chunks): every wavefront
+            // finds these cells (the same decisions), takes its share of them,
+            // and drops their chunks from the per-chunk work
+            unsigned long long todo = far, taken = 0;
+            while (todo) {
+                const int b = __builtin_ctzll(todo) & ~(kFarCellChunks - 1);
+                todo &= ~(((1ull << kFarCellChunks) - 1) << b);
+                const int c = c0 + b;
+                const int nc = nch - c < kFarCellChunks ? nch - c : kFarCellChunks;
+                const unsigned long long need = ((1ull << nc) - 1) << b;
+                if ((far & need) != need) continue;
+                const double* rec = cells + (long)(c / kFarCellChunks) * kChunkRec;
+                const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
+                const double rho2 = zr * zr + zi * zi;
+                if (rho2 > 0.0 && rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
+                    taken |= need;
+                    if ((c / kFarCellChunks) % kFarWaves == wave) {
+                        any = 1;
+                        m2p(rec, zr, zi, rho2);
+                    }
+                }
+            }
+            far &= ~taken;
+        }
+        far &= mine;
         while (far) {
             const int c = c0 + __builtin_ctzll(far);
             far &= far - 1;
@@ -342,34 +440,8 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
                 const double* rec = cmp + (long)c * kChunkRec;
                 const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
                 const double rho2 = zr * zr + zi * zi;
-                if (rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
-                    if (lane <= kFarPM) {
-                        // lane n: T_p += B_n hol[n + p] lambda_j^p zeta^{-(n + p)}, p = 1 .. 2M
-                        const double br = rec[4 + 2 * lane], bi = rec[5 + 2 * lane];
-                        const double id = 1.0 / rho2;
-                        const double z1r = zr * id, z1i = -zi * id;  // 1 / zeta
-                        double wr = 1.0, wi = 0.0, qr = z1r, qi = z1i;
-                        for (int e = lane + 1; e; e >>= 1) {  // zeta^{-(n + 1)}
-                            if (e & 1) {
-                                const double t = wr * qr - wi * qi;
-                                wi = wr * qi + wi * qr;
-                                wr = t;
-                            }
-                            const double t = qr * qr - qi * qi;
-                            qi = 2.0 * qr * qi;
-                            qr = t;
-                        }
-                        double vr = kPairHolFar[lane + 1] * lj * wr, vi = kPairHolFar[lane + 1] * lj * wi;
-                        const double ur = lj * z1r, ui = lj * z1i;  // lambda_j / zeta
-                        sfor<1, GM + 1>([&](auto p) {
-                            Tr[p] += br * vr - bi * vi;
-                            Ti[p] += br * vi + bi * vr;
-                            const double f = -(double)(lane + p);  // hol[m + 1] / hol[m] = -m
-                            const double nr = (vr * ur - vi * ui) * f, ni = (vr * ui + vi * ur) * f;
-                            vr = nr;
-                            vi = ni;
-                        });
-                    }
+                if (rho2 > 0.0 && rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
+                    m2p(rec, zr, zi, rho2);
                     continue;
                 }
             }
@@ -453,6 +525,7 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
 // chunk's field as sum_n B_n L^(n)(z - z_c),
 //   B_n = sum_q sum_{s <= min(n, M)} Qu_{q,s} (-d_q)^{n-s} / (n-s)!,  d_q = z_q - z_c,
 // convergent for |z - z_c| > max |d_q| (the chunk radius), kept to n = kFarPM.
+// The record: centre, radius, the largest lambda^2 of the chunk, then B_n.
 // One workgroup per chunk, lane = source.  Every wavefront forms the centre
 // (the same shuffle trees, so the same bits), its sources' multipoles and the
 // factors (-d)^m / m! by their recurrence; wavefront w keeps the per-source
@@ -482,11 +555,16 @@ __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* _
     const double c1 = s1 / cnt, c2 = s2 / cnt;
     const double d1 = live ? x1 - c1 : 0.0, d2 = live ? x2 - c2 : 0.0;
     double r2 = d1 * d1 + d2 * d2;
-    for (int off = 32; off > 0; off >>= 1) r2 = fmax(r2, __shfl_xor(r2, off, 64));
+    const double l2q = live ? lam2[q] : 0.0;
+    double l2m = l2q;
+    for (int off = 32; off > 0; off >>= 1) {
+        r2 = fmax(r2, __shfl_xor(r2, off, 64));
+        l2m = fmax(l2m, __shfl_xor(l2m, off, 64));
+    }
     double qr[M + 1], qi[M + 1];
     sfor<0, M + 1>([&](auto s) { qr[s] = 0.0; qi[s] = 0.0; });
     if (live) {
-        const double lq = sqrt(lam2[q]);
+        const double lq = sqrt(l2q);
         double lp = 1.0;  // lambda_q^s: the unscaled moments M = alpha lambda^{|m|}
         sfor<0, M + 1>([&](auto s) {
             sfor<0, s + 1>([&](auto m2) {
@@ -504,7 +582,7 @@ __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* _
         rec[0] = c1;
         rec[1] = c2;
         rec[2] = sqrt(r2);
-        rec[3] = 0.0;
+        rec[3] = l2m;  // the largest lambda^2 of the chunk (for the near kernel's far test)
     }
     // e_k = (-d)^k / k!: er[s], ei[s] hold e_{n - s} (zero for n - s < 0)
     const int n0 = wave * kMpPerWave, n1 = n0 + kMpPerWave < kMpTerms ? n0 + kMpPerWave : kMpTerms;
@@ -550,6 +628,81 @@ __global__ __launch_bounds__(256) void k_chunk_multipoles(int N, const double* _
     }
 }
 
+// Expansion of each cell of kFarCellChunks consecutive chunks about its centre
+// z_K (the mean of its sources' positions, from the chunks' centres and source
+// counts), translated from the chunks' expansions: with delta_c = z_c - z_K,
+//   B^K_n = sum_c sum_{k <= n} B^c_k (-delta_c)^{n-k} / (n-k)!
+// (term n needs the chunks' terms up to n only, so the truncation is theirs);
+// radius max_c (|delta_c| + r_c).  A workgroup per cell, wavefront w = chunk w
+// of the cell, lane n = term; the chunks' terms meet in LDS and are added in
+// chunk order.  (Instantiated per order only to live in the unit of that order.)
+template <int M>
+__global__ __launch_bounds__(256) void k_cell_multipoles(int N, const double* __restrict__ cmp,
+                                                         double* __restrict__ cells)
+{
+    static_assert(kFarCellChunks * 64 == 256, "a wavefront per chunk of the cell");
+    __shared__ double sb[kFarCellChunks][2 * kMpTerms];
+    __shared__ double sa[kFarCellChunks][2 * kMpTerms];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, k = blockIdx.x;
+    const int nch = (N + 63) >> 6, cfirst = k * kFarCellChunks;
+    for (int e = threadIdx.x; e < kFarCellChunks * 2 * kMpTerms; e += 256) {
+        const int w = e / (2 * kMpTerms), t = e - w * (2 * kMpTerms);
+        sb[w][t] = cfirst + w < nch ? cmp[(long)(cfirst + w) * kChunkRec + 4 + t] : 0.0;
+    }
+    // centre and radius (every thread the same values, chunks in order)
+    double s1 = 0.0, s2 = 0.0, cnt = 0.0;
+    for (int w = 0; w < kFarCellChunks && cfirst + w < nch; ++w) {
+        const double* r = cmp + (long)(cfirst + w) * kChunkRec;
+        const int left = N - (cfirst + w) * 64;
+        const double n = (double)(left < 64 ? left : 64);
+        s1 += n * r[0];
+        s2 += n * r[1];
+        cnt += n;
+    }
+    const double z1 = s1 / cnt, z2 = s2 / cnt;
+    double rad = 0.0, l2m = 0.0;
+    for (int w = 0; w < kFarCellChunks && cfirst + w < nch; ++w) {
+        const double* r = cmp + (long)(cfirst + w) * kChunkRec;
+        const double e1 = r[0] - z1, e2 = r[1] - z2;
+        rad = fmax(rad, sqrt(e1 * e1 + e2 * e2) + r[2]);
+        l2m = fmax(l2m, r[3]);
+    }
+    __syncthreads();
+    if (lane < kMpTerms) {
+        double ar = 0.0, ai = 0.0;
+        if (cfirst + wave < nch) {
+            const double* r = cmp + (long)(cfirst + wave) * kChunkRec;
+            const double d1 = z1 - r[0], d2 = z2 - r[1];  // -delta_c
+            double er = 1.0, ei = 0.0;                    // (-delta_c)^m / m!
+            for (int m = 0; m <= lane; ++m) {
+                const double br = sb[wave][2 * (lane - m)], bi = sb[wave][2 * (lane - m) + 1];
+                ar += br * er - bi * ei;
+                ai += br * ei + bi * er;
+                const double f = 1.0 / (double)(m + 1);
+                const double nr = (er * d1 - ei * d2) * f, ni = (er * d2 + ei * d1) * f;
+                er = nr;
+                ei = ni;
+            }
+        }
+        sa[wave][2 * lane] = ar;
+        sa[wave][2 * lane + 1] = ai;
+    }
+    __syncthreads();
+    double* rec = cells + (long)k * kChunkRec;
+    const int t = threadIdx.x;
+    if (t < 2 * kMpTerms) {
+        double v = sa[0][t];
+        for (int w = 1; w < kFarCellChunks; ++w) v += sa[w][t];
+        rec[4 + t] = v;
+    }
+    if (t == 0) {
+        rec[0] = z1;
+        rec[1] = z2;
+        rec[2] = rad;
+        rec[3] = l2m;
+    }
+}
+
 template <int M>
 hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f32, PairShape sh, hipStream_t st)
 {
@@ -566,35 +719,50 @@ hipError_t launch_pair_M(const DevTables& T, const StageBufs& B, int cur, bool f
     const double* lt = B.lam2[cur];
     const double* xsrc = B.xsS;
     const double* lsrc = B.lam2S[cur];
+    // With the far split and sorted sources the chunk records come first: the
+    // near kernel reads them to skip provably far chunks, the far kernel takes
+    // distant chunks (and cells of kFarCellChunks chunks) through their
+    // expansions.  MMVM_FAR_M2P=0 keeps every far pair on the pairwise form,
+    // MMVM_FAR_CELLS=0 the chunk expansions but not the cells'.
+    const bool recs = sh.far && B.rank && B.chunk_mp;
+    const char* env = std::getenv("MMVM_FAR_M2P");
+    const bool m2p = !(env && env[0] == '0');
+    const double* cmp = (recs && m2p) ? B.chunk_mp : nullptr;
+    const int nch = (B.N + 63) >> 6, ncell = (nch + kFarCellChunks - 1) / kFarCellChunks;
+    const char* cenv = std::getenv("MMVM_FAR_CELLS");
+    // one cell holds every source (the target's own among them): never used
+    double* cells = (cmp && ncell > 1 && !(cenv && cenv[0] == '0')) ? B.chunk_mp + (long)nch * kChunkRec : nullptr;
+    if (recs) {
+        TimingSlot* outer = timing_slot();  // the caller's slot times the near kernel
+        timing_slot() = nullptr;
+        void* tk = timing_begin(st);
+        launch_kernel((k_chunk_multipoles<M>), dim3(nch), dim3(256), 0, st, B.N, xsrc, lsrc,
+                      (const double*)B.alphaT[cur], B.chunk_mp);
+        if (cells)
+            launch_kernel((k_cell_multipoles<M>), dim3(ncell), dim3(256), 0, st, B.N, (const double*)B.chunk_mp,
+                          cells);
+        timing_end(tk, "pair_mp", st);
+        timing_slot() = outer;
+    }
+    const double* crec = recs ? B.chunk_mp : nullptr;
     if (use32 && sh.far)
         launch_kernel((k_pair<M, float, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc, lsrc,
-                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank);
+                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank, crec);
     else if (use32)
         launch_kernel((k_pair<M, float, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc, lsrc,
-                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank);
+                      (const float*)B.alphaT32[cur], B.s_pair, B.far_mask, B.rank, (const double*)nullptr);
     else if (sh.far)
         launch_kernel((k_pair<M, double, true>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc,
-                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank);
+                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank, crec);
     else
         launch_kernel((k_pair<M, double, false>), grid, dim3(64 * waves), shmem, st, B.N, sh.split, xt, lt, xsrc,
-                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank);
+                      lsrc, (const double*)B.alphaT[cur], B.s_pair, B.far_mask, B.rank, (const double*)nullptr);
     if (sh.far) {
-        // chunk expansions (sorted sources only: unsorted chunks are not compact);
-        // MMVM_FAR_M2P=0 keeps every far pair on the pair-by-pair form
-        const char* env = std::getenv("MMVM_FAR_M2P");
-        const bool m2p = !(env && env[0] == '0');
-        const double* cmp = (m2p && B.rank && B.chunk_mp) ? B.chunk_mp : nullptr;
-        if (cmp) {
-            const int nch = (B.N + 63) >> 6;
-            void* tk = timing_begin(st);
-            launch_kernel((k_chunk_multipoles<M>), dim3(nch), dim3(256), 0, st, B.N, xsrc, lsrc,
-                          (const double*)B.alphaT[cur], B.chunk_mp);
-            timing_end(tk, "pair_mp", st);
-        }
         // timed on its own (the caller's slot took the near kernel)
         void* tk = timing_begin(st);
         launch_kernel((k_pair_far<M>), dim3(B.N), dim3(kFarThreads), 0, st, B.N, xt, lt, xsrc, lsrc,
-                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.rank, cmp, B.s_pair);
+                      (const double*)B.alphaT[cur], (const unsigned char*)B.far_mask, B.rank, cmp,
+                      (const double*)cells, B.s_pair);
         timing_end(tk, "pair_far", st);
     }
     return hipGetLastError();

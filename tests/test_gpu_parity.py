@@ -774,6 +774,71 @@ def test_mixed_bound_from_decaying_to_flat_spectra(env, orc, N, M, decay, amp):
     assert err <= bar and errx <= MIXED_TOL
 
 
+@pytest.mark.parametrize("N,M,spacing", [(4096, 4, 4.0), (8000, 2, 3.0), (5000, 6, 4.0)])
+def test_far_field_cell_expansions_match_chunks(env, orc, N, M, spacing):
+    """Cells of four consecutive sorted chunks carry an expansion translated
+    from their chunks'; a target far from a whole cell takes it once instead of
+    four chunk expansions.  On a field wide enough for many such cells the
+    right-hand side equals the chunk expansions alone (MMVM_FAR_CELLS=0) and the
+    pairwise far field (MMVM_FAR_M2P=0) to rounding, differs from the chunk
+    expansions alone (the cells are used), and matches the oracle's sampled
+    rows to the FP64 bar."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    w = wl.dilute_multi(N=N, M=M, seed=80 + M, spacing=spacing)
+    structure(w, 81 + M)
+    t = 0.1
+    res = {}
+    for name, var in (("pairwise", "MMVM_FAR_M2P"), ("chunks", "MMVM_FAR_CELLS")):
+        os.environ[var] = "0"
+        try:
+            res[name] = gpu_rhs(env, w, t, 0)
+        finally:
+            os.environ.pop(var, None)
+    dx_c, dm_c = gpu_rhs(env, w, t, 0)
+    lam_t = np.sqrt(w.lam0 ** 2 + 4 * w.nu * t)
+    assert not np.array_equal(dm_c, res["chunks"][1])
+    for name in ("pairwise", "chunks"):
+        dx_r, dm_r = res[name]
+        assert normwise(M, lam_t, dm_r, dm_c, w.mom[:, 0], dx_r) <= 1e-13, name
+        assert np.abs(dx_c - dx_r).max() <= 1e-13 * np.abs(dx_r).max(), name
+    js = [0, N // 2, N - 1]
+    rj = [j for j in js for _ in range(w.K)]
+    rk = [k for _ in js for k in range(w.K)]
+    d, dxr = orc.rhs_rows(w.M, w.nu, w.lam0, t, w.x, w.mom, rj, rk)
+    dx_r = dxr.reshape(3, w.K, 2)[:, 0, :]
+    assert normwise(M, lam_t[js], d.reshape(3, w.K), dm_c[js], w.mom[js, 0], dx_r) <= FP64_TOL
+    assert np.abs(dx_c[js] - dx_r).max() <= FP64_TOL * np.abs(dx_r).max()
+
+
+def test_far_mask_of_a_chunk_holding_only_the_target(env):
+    """N = 1089 leaves one source in the last sorted chunk.  A first call marks
+    that chunk far for the targets away from its source; a second call on the
+    mirrored field puts another vortex alone there, whose own chunk must then
+    read near (not a stale far byte of the first call, which would send a
+    zero-distance chunk to the expansion): every row of the second call equals
+    the near form of the default shape to rounding."""
+    torch, mm = env
+    from paper_1010_2475_amd import workloads as wl
+    N, M = 1089, 2
+    w = wl.dilute_multi(N=N, M=M, seed=90)
+    structure(w, 91)
+    gpu_rhs(env, w, 0.1, 0)
+    w2 = wl.dilute_multi(N=N, M=M, seed=90)
+    w2.mom = w.mom.copy()
+    w2.x = -w.x
+    dx_f, dm_f = gpu_rhs(env, w2, 0.1, 0)
+    mm.autotune_enable(False)
+    try:
+        dx_n, dm_n = gpu_rhs(env, w2, 0.1, 0)
+    finally:
+        mm.autotune_enable(True)
+    assert np.isfinite(dm_f).all() and np.isfinite(dx_f).all()
+    lam_t = np.sqrt(w2.lam0 ** 2 + 4 * w2.nu * 0.1)
+    assert normwise(M, lam_t, dm_n, dm_f, w2.mom[:, 0], dx_n) <= 1e-13
+    assert np.abs(dx_f - dx_n).max() <= 1e-13 * np.abs(dx_n).max()
+
+
 @pytest.mark.parametrize("N,M", [(4096, 4), (3000, 6), (2048, 2)])
 def test_far_field_chunk_expansions_match_pairwise(env, orc, N, M):
     """Far chunks that lie well away from a target (radius <= 0.3 of the
