@@ -88,12 +88,12 @@ def pair_flops(M):
 # from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a
 # plain device copy of known size (bench.py --copy-calibration: 256 MiB read
-# and written per launch; FETCH_SIZE read 131084.6 KiB, WRITE_SIZE 262146.3 KiB).
+# and written per launch; FETCH_SIZE read 131084.8 KiB, WRITE_SIZE 262147.5 KiB).
 # Valid only for the kernel sources it was taken on.
-TRAFFIC_STAGE2 = {"fetch_kib": 3243.8, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.6,
-                  "write_scale": 262144.0 / 262146.3,
-                  "sources_sha256": {"kernels.hip": "084e89d6f753b7e7649874c86711968478306c744654ecc89d8d1f2b17964336",
-                                     "kernels.hpp": "6624c40ccd4fb1d9097d57e832da7ac9982776aecf7471c2d3b01cfe9c91b294"}}
+TRAFFIC_STAGE2 = {"fetch_kib": 3239.8, "write_kib": 169.1, "fetch_scale": 262144.0 / 131084.8,
+                  "write_scale": 262144.0 / 262147.5,
+                  "sources_sha256": {"kernels.hip": "8f022ac73420ed8a2e648137bffa0701a374aafb67440319d8608db3f54760d4",
+                                     "kernels.hpp": "a0d7a78e1c6f36cd875dd4c34788830eaaf17b6e5eb04a464db3aa2561c309d2"}}
 
 
 def stage2_traffic_bytes():
