@@ -114,41 +114,8 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     if constexpr (F32) sfor<0, KG>([&](auto g) { acc32[g] = 0.0f; });
     int pending = 0;
 
-    const int nch = (N + 63) >> 6;
-    unsigned long long bfar = 0;  // chunks bbase .. bbase + 63 provably far (FAR with records)
-    int bbase = -64;
-    for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split) {
-        const bool own = jp == self;
-        if constexpr (!FAR) {
-            if (own) continue;
-        }
-        if constexpr (FAR) {
-            // a chunk whose record (centre, radius r_c, largest lambda^2) puts
-            // every source beyond the threshold is far without reading its
-            // sources: |x_j - x_q| >= rho - r_c, so w_q >= (rho - r_c)^2 /
-            // (lambda_j^2 + max lambda^2).  The records of 64 chunks at a time,
-            // one per lane; the other chunks take the exact test below (the
-            // same mask either way, up to a margin of rounding)
-            if (crec) {
-                const int c = jp >> 6;  // uniform: the lanes hold one chunk
-                if (c >= bbase + 64) {
-                    bbase = c & ~63;
-                    bool bf = false;
-                    const int cc = bbase + lane;
-                    if (cc < nch) {
-                        const double* r = crec + (long)cc * kChunkRec;
-                        const double e1 = xj1 - r[0], e2 = xj2 - r[1];
-                        const double gap = sqrt(e1 * e1 + e2 * e2) - r[2];
-                        bf = gap > 0.0 && gap * gap > kFarBoundMargin * pair_far_w(P) * (lj2 + r[3]);
-                    }
-                    bfar = __ballot(bf);
-                }
-                if ((bfar >> (c - bbase)) & 1ull) {
-                    if (jp == c * 64) farmask[(long)j * pair_mask_stride(N) + c] = 1;
-                    continue;
-                }
-            }
-        }
+    // one source per lane: the pair (target j, source jp) added into acc
+    auto visit = [&](int jp, bool own) {
         const double lp2 = lam2[jp];
         const double c = lj2 + lp2;
         const double isc = 1.0 / sqrt(c);
@@ -160,7 +127,7 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
             // count, and a chunk holding nothing else is near
             const bool all_far = __all(own || w > pair_far_w(P)) && __any(!own);  // uniform over the wavefront
             farmask[(long)j * pair_mask_stride(N) + (jp >> 6)] = all_far ? 1 : 0;
-            if (all_far || own) continue;
+            if (all_far || own) return;
         }
         const double e1 = exp(-s1 * s1), e2 = exp(-s2 * s2);
         const double E = e1 * e2;
@@ -290,6 +257,46 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
                 pending = 0;
             }
         }
+    };
+    const int nch = (N + 63) >> 6;
+    if constexpr (FAR) {
+        if (crec) {
+            // A chunk whose record (centre, radius r_c, largest lambda^2) puts
+            // every source beyond the threshold is far without reading its
+            // sources: |x_j - x_q| >= rho - r_c, so w_q >= (rho - r_c)^2 /
+            // (lambda_j^2 + max lambda^2).  The records of 64 chunks at a time,
+            // one per lane: the provably far ones are flagged with one store, and
+            // the wavefront visits only the others of its share (chunk
+            // c = sp mod split, in increasing order as below), which take the
+            // exact test (the same flags either way, up to a margin of rounding).
+            const unsigned long long mine = split == 1   ? ~0ull
+                                            : split == 2 ? 0x5555555555555555ull << sp
+                                                         : 0x1111111111111111ull << sp;
+            for (int g0 = 0; live && g0 < nch; g0 += 64) {
+                const int cc = g0 + lane;
+                bool bf = false;
+                if (cc < nch) {
+                    const double* r = crec + (long)cc * kChunkRec;
+                    const double e1 = xj1 - r[0], e2 = xj2 - r[1];
+                    const double gap = sqrt(e1 * e1 + e2 * e2) - r[2];
+                    bf = gap > 0.0 && gap * gap > kFarBoundMargin * pair_far_w(P) * (lj2 + r[3]);
+                }
+                if (bf && (cc & (split - 1)) == sp) farmask[(long)j * pair_mask_stride(N) + cc] = 1;
+                const unsigned long long valid = nch - g0 >= 64 ? ~0ull : (1ull << (nch - g0)) - 1;
+                unsigned long long todo = ~__ballot(bf) & valid & mine;  // uniform per wavefront
+                while (todo) {
+                    const int c = g0 + __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    const int jp = c * 64 + lane;
+                    if (jp < N) visit(jp, jp == self);
+                }
+            }
+        } else {
+            for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split) visit(jp, jp == self);
+        }
+    } else {
+        for (int jp = sp * 64 + lane; live && jp < N; jp += 64 * split)
+            if (jp != self) visit(jp, false);
     }
     if constexpr (F32) sfor<0, KG>([&](auto g) { acc[g] += (double)acc32[g]; });
 
