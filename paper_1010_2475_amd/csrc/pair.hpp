@@ -327,18 +327,30 @@ __global__ __launch_bounds__(kPairMaxThreads) void k_pair(int N, int split, cons
     }
 }
 
-// The pairs of the chunks marked far, one wavefront per target (lanes over the
-// 64 sources of a chunk), added to the pair table after the near kernel (FP64
-// in both precisions; the same multipole form for every shape):
+// Orders LDS writes of some lanes of a wavefront before later reads by other
+// lanes of the same wavefront (its LDS operations complete in order).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The pairs of the chunks marked far, added to the pair table after the near
+// kernel (FP64 in both precisions; the same multipole form for every shape):
 //   Q_s = sum_{|m| = s} alpha'_m i^{m2},  T_p = sum_s Q_s H_{s+p},
 //   S[g] += 2 Re(i^{g2} T_{|g|}),  H_n = hol[n] (lambda_j / Delta z)^n,
-// Delta z = (x^j - x^{j'})_1 + i (x^j - x^{j'})_2, generated shell by shell.
-// The wavefront reads the flags of 64 chunks at once (lane c: chunk c) and
-// visits the set ones only, so a target with no far chunk costs one load.
-// A workgroup of kFarWaves wavefronts takes one target, wavefront q the far
-// chunks c = q mod kFarWaves (the far chunks of a target tend to be runs of
+// Delta z = (x^j - x^{j'})_1 + i (x^j - x^{j'})_2, generated shell by shell
+// (lanes over the 64 sources of a chunk), or for a whole chunk or cell through
+// its expansion where that converges (queued, several per wavefront pass).
+// A workgroup of kFarWaves wavefronts takes one target.  For each group of 64
+// chunks every wavefront reads the flags, the chunk and the cell decisions
+// lane-parallel (one record load per lane), then takes its share: the
+// accepted cells k = q mod kFarWaves and the other far chunks
+// c = q mod kFarWaves (the far chunks of a target tend to be runs of
 // consecutive sorted chunks: the targets at the edge of a dense region carry
-// many, the others none); the wavefront sums meet in LDS in wavefront order.
+// many, the others none).  A target with no far chunk costs one load per
+// group; the wavefront sums meet in LDS in wavefront order.
 constexpr int kFarWaves = 4;
 constexpr int kFarThreads = 64 * kFarWaves;
 
@@ -379,79 +391,124 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
     // entries g once, after the wavefront sum)
     double Tr[GM + 1], Ti[GM + 1];
     sfor<1, GM + 1>([&](auto p) { Tr[p] = 0.0; Ti[p] = 0.0; });
-    // an expansion record (chunk or cell) at zeta = z_j - z_c, rho2 = |zeta|^2:
-    // lane n adds T_p += B_n hol[n + p] lambda_j^p zeta^{-(n + p)}, p = 1 .. 2M
-    auto m2p = [&](const double* rec, double zr, double zi, double rho2) {
-        if (lane > kFarPM) return;
-        const double br = rec[4 + 2 * lane], bi = rec[5 + 2 * lane];
-        const double id = 1.0 / rho2;
-        const double z1r = zr * id, z1i = -zi * id;  // 1 / zeta
-        double wr = 1.0, wi = 0.0, qr = z1r, qi = z1i;
-        for (int e = lane + 1; e; e >>= 1) {  // zeta^{-(n + 1)}
-            if (e & 1) {
-                const double t = wr * qr - wi * qi;
-                wi = wr * qi + wi * qr;
-                wr = t;
-            }
-            const double t = qr * qr - qi * qi;
-            qi = 2.0 * qr * qi;
-            qr = t;
+    // Expansions (chunk or cell records) are queued per wavefront and evaluated
+    // kRB at a time: lane (g, p - 1) takes queued record g and derivative order
+    // p, S_p = sum_n hol[n + p] B_n u^n by Horner's rule in u = 1 / zeta
+    // (zeta = z_j - z_c), then T_p += (lambda_j u)^p S_p.  The coefficients of
+    // a batch are staged in LDS (one lane-parallel copy), the factors hol[m]
+    // once per workgroup.
+    constexpr int kPL = GM <= 8 ? 8 : 16;  // lanes per queued record
+    constexpr int kRB = 64 / kPL;          // records per batch
+    constexpr int kBT = 2 * (kFarPM + 1);  // doubles of B in a record
+    __shared__ double hol_s[kFarPM + GM + 1];
+    __shared__ double bq[kFarWaves][kRB][kBT];
+    __shared__ int qid[kFarWaves][kRB];
+    for (int i = threadIdx.x; i <= kFarPM + GM; i += kFarThreads) hol_s[i] = kPairHolFar[i];
+    __syncthreads();
+    int qn = 0;  // queued records of this wavefront (uniform)
+    // the expansions' T_p of this lane's fixed p = lane mod kPL + 1, added into
+    // the sum over lanes of T_p at the end (a separate register: no indexing of
+    // T by a lane-dependent p)
+    const int ep = lane % kPL + 1;
+    double er = 0.0, ei = 0.0;
+    auto flush = [&]() __attribute__((always_inline)) {
+        wave_lds_sync();
+        for (int e = lane; e < qn * kBT; e += 64) {
+            const int r = e / kBT, t = e - r * kBT;
+            bq[wave][r][t] = cmp[(long)qid[wave][r] * kChunkRec + 4 + t];
         }
-        double vr = kPairHolFar[lane + 1] * lj * wr, vi = kPairHolFar[lane + 1] * lj * wi;
-        const double ur = lj * z1r, ui = lj * z1i;  // lambda_j / zeta
-        sfor<1, GM + 1>([&](auto p) {
-            Tr[p] += br * vr - bi * vi;
-            Ti[p] += br * vi + bi * vr;
-            const double f = -(double)(lane + p);  // hol[m + 1] / hol[m] = -m
-            const double nr = (vr * ur - vi * ui) * f, ni = (vr * ui + vi * ur) * f;
-            vr = nr;
-            vi = ni;
-        });
+        wave_lds_sync();
+        const int g = lane / kPL, p = ep;
+        if (g < qn && p <= GM) {
+            const double* rec = cmp + (long)qid[wave][g] * kChunkRec;
+            const double zr = xj1 - rec[0], zi = xj2 - rec[1];
+            const double id = 1.0 / (zr * zr + zi * zi);
+            const double ur = zr * id, ui = -zi * id;  // 1 / zeta
+            const double* b = bq[wave][g];
+            double sr = 0.0, si = 0.0;
+#pragma unroll 2
+            for (int n = kFarPM; n >= 0; --n) {
+                const double h = hol_s[n + p];
+                const double tr = sr * ur - si * ui + h * b[2 * n];
+                si = sr * ui + si * ur + h * b[2 * n + 1];
+                sr = tr;
+            }
+            double wr = 1.0, wi = 0.0, qr = lj * ur, qi = lj * ui;
+            for (int e = p; e; e >>= 1) {  // (lambda_j u)^p
+                if (e & 1) {
+                    const double t = wr * qr - wi * qi;
+                    wi = wr * qi + wi * qr;
+                    wr = t;
+                }
+                const double t = qr * qr - qi * qi;
+                qi = 2.0 * qr * qi;
+                qr = t;
+            }
+            er += sr * wr - si * wi;
+            ei += sr * wi + si * wr;
+        }
+        wave_lds_sync();  // the queue and the staged coefficients are reused
+        qn = 0;
+    };
+    auto push = [&](const double* rec) __attribute__((always_inline)) {
+        if (lane == 0) qid[wave][qn] = (int)((rec - cmp) / kChunkRec);
+        if (++qn == kRB) flush();
     };
     int any = 0;  // this wavefront had far chunks
+    static_assert(64 / kFarCellChunks <= 64, "a lane per cell of a group");
     for (int c0 = 0; c0 < nch; c0 += 64) {
+        // the decisions of a group of 64 chunks, lane-parallel (one record load
+        // each): flag, chunk expansion converging here, cell expansion
+        // converging here for cells whose chunks are all far
         const bool flag = c0 + lane < nch && row[c0 + lane] != 0;
         unsigned long long far = __ballot(flag);  // uniform per wavefront
-        any |= (far & mine) != 0;
+        bool cexp = false;
+        if (cmp && flag) {
+            const double* rec = cmp + (long)(c0 + lane) * kChunkRec;
+            const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
+            const double rho2 = zr * zr + zi * zi;
+            cexp = rho2 > 0.0 && rc * rc <= kTheta2 * rho2;
+        }
+        const unsigned long long chunk_exp = __ballot(cexp);
         if (cells) {
             // a cell whose chunks are all far takes its own expansion where that
             // converges (one record for kFarCellChunks chunks): every wavefront
-            // finds these cells (the same decisions), takes its share of them,
-            // and drops their chunks from the per-chunk work
-            unsigned long long todo = far, taken = 0;
-            while (todo) {
-                const int b = __builtin_ctzll(todo) & ~(kFarCellChunks - 1);
-                todo &= ~(((1ull << kFarCellChunks) - 1) << b);
-                const int c = c0 + b;
+            // has the same decisions, takes its share of these cells, and drops
+            // their chunks from the per-chunk work
+            bool kexp = false;
+            const int b = kFarCellChunks * lane, c = c0 + b;
+            if (lane < 64 / kFarCellChunks && c < nch) {
                 const int nc = nch - c < kFarCellChunks ? nch - c : kFarCellChunks;
                 const unsigned long long need = ((1ull << nc) - 1) << b;
-                if ((far & need) != need) continue;
-                const double* rec = cells + (long)(c / kFarCellChunks) * kChunkRec;
-                const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
-                const double rho2 = zr * zr + zi * zi;
-                if (rho2 > 0.0 && rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
-                    taken |= need;
-                    if ((c / kFarCellChunks) % kFarWaves == wave) {
-                        any = 1;
-                        m2p(rec, zr, zi, rho2);
-                    }
+                if ((far & need) == need) {
+                    const double* rec = cells + (long)(c / kFarCellChunks) * kChunkRec;
+                    const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
+                    const double rho2 = zr * zr + zi * zi;
+                    kexp = rho2 > 0.0 && rc * rc <= kTheta2 * rho2;
+                }
+            }
+            unsigned long long kq = __ballot(kexp), taken = 0;
+            while (kq) {
+                const int k = __builtin_ctzll(kq);
+                kq &= kq - 1;
+                taken |= ((1ull << kFarCellChunks) - 1) << (kFarCellChunks * k);
+                if (k % kFarWaves == wave) {
+                    any = 1;
+                    push(cells + (long)((c0 >> 6) * (64 / kFarCellChunks) + k) * kChunkRec);
                 }
             }
             far &= ~taken;
         }
         far &= mine;
+        any |= far != 0;
         while (far) {
             const int c = c0 + __builtin_ctzll(far);
-            far &= far - 1;
-            if (cmp) {
-                const double* rec = cmp + (long)c * kChunkRec;
-                const double zr = xj1 - rec[0], zi = xj2 - rec[1], rc = rec[2];
-                const double rho2 = zr * zr + zi * zi;
-                if (rho2 > 0.0 && rc * rc <= kTheta2 * rho2) {  // uniform per wavefront (one target)
-                    m2p(rec, zr, zi, rho2);
-                    continue;
-                }
+            if ((chunk_exp >> (c - c0)) & 1ull) {
+                far &= far - 1;
+                push(cmp + (long)c * kChunkRec);
+                continue;
             }
+            far &= far - 1;
             const int jp = c * 64 + lane;
             if (jp >= N || jp == self) continue;
             const double lp2 = lam2[jp];
@@ -494,10 +551,11 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
             });
         }
     }
+    if (qn) flush();
     // a target without far chunks (most of a dense field) leaves here
     if (!__syncthreads_or(any)) return;
     sfor<1, GM + 1>([&](auto p) {
-        double vr = Tr[p], vi = Ti[p];
+        double vr = Tr[p] + (ep == p ? er : 0.0), vi = Ti[p] + (ep == p ? ei : 0.0);
         for (int off = 32; off > 0; off >>= 1) {
             vr += __shfl_xor(vr, off, 64);
             vi += __shfl_xor(vi, off, 64);
