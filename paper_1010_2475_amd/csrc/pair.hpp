@@ -396,15 +396,15 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
     // p, S_p = sum_n hol[n + p] B_n u^n by Horner's rule in u = 1 / zeta
     // (zeta = z_j - z_c), then T_p += (lambda_j u)^p S_p.  The coefficients of
     // a batch are staged in LDS (one lane-parallel copy), the factors hol[m]
-    // once per workgroup.
+    // once per wavefront.
     constexpr int kPL = GM <= 8 ? 8 : 16;  // lanes per queued record
     constexpr int kRB = 64 / kPL;          // records per batch
     constexpr int kBT = 2 * (kFarPM + 1);  // doubles of B in a record
-    __shared__ double hol_s[kFarPM + GM + 1];
+    static_assert(kFarPM + GM < 64, "a lane per factor hol[m]");
+    __shared__ double hol_s[kFarWaves][kFarPM + GM + 1];  // a copy per wavefront: no workgroup barrier
     __shared__ double bq[kFarWaves][kRB][kBT];
     __shared__ int qid[kFarWaves][kRB];
-    for (int i = threadIdx.x; i <= kFarPM + GM; i += kFarThreads) hol_s[i] = kPairHolFar[i];
-    __syncthreads();
+    if (lane <= kFarPM + GM) hol_s[wave][lane] = kPairHolFar[lane];
     int qn = 0;  // queued records of this wavefront (uniform)
     // the expansions' T_p of this lane's fixed p = lane mod kPL + 1, added into
     // the sum over lanes of T_p at the end (a separate register: no indexing of
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
             double sr = 0.0, si = 0.0;
 #pragma unroll 2
             for (int n = kFarPM; n >= 0; --n) {
-                const double h = hol_s[n + p];
+                const double h = hol_s[wave][n + p];
                 const double tr = sr * ur - si * ui + h * b[2 * n];
                 si = sr * ui + si * ur + h * b[2 * n + 1];
                 sr = tr;
