@@ -455,7 +455,6 @@ __global__ __launch_bounds__(kFarThreads) void k_pair_far(int N, const double* _
         if (++qn == kRB) flush();
     };
     int any = 0;  // this wavefront had far chunks
-    static_assert(64 / kFarCellChunks <= 64, "a lane per cell of a group");
     for (int c0 = 0; c0 < nch; c0 += 64) {
         // the decisions of a group of 64 chunks, lane-parallel (one record load
         // each): flag, chunk expansion converging here, cell expansion
