@@ -714,7 +714,8 @@ def test_high_order_stepping_matches_oracle_golden(env, prec):
         assert m_g[0, 0] == w.mom[0, 0]
 
 
-@pytest.mark.parametrize("N,M,prec", [(2000, 4, 0), (2000, 6, 0), (2000, 4, 1), (1025, 2, 0), (1089, 3, 1)])
+@pytest.mark.parametrize("N,M,prec", [(2000, 4, 0), (2000, 6, 0), (2000, 4, 1), (1025, 2, 0), (1089, 3, 1),
+                                    (1100, 0, 0), (1500, 1, 1), (2000, 5, 0)])
 def test_far_field_dilute_matches_oracle(env, orc, N, M, prec):
     """A dilute field (mean spacing 2, cores 0.2-0.5): with the sources sorted
     in space, most 64-source chunks of a target are entirely beyond the
@@ -774,7 +775,7 @@ def test_mixed_bound_from_decaying_to_flat_spectra(env, orc, N, M, decay, amp):
     assert err <= bar and errx <= MIXED_TOL
 
 
-@pytest.mark.parametrize("N,M,spacing", [(4096, 4, 4.0), (8000, 2, 3.0), (5000, 6, 4.0)])
+@pytest.mark.parametrize("N,M,spacing", [(4096, 4, 4.0), (8000, 2, 3.0), (5000, 6, 4.0), (4500, 5, 4.0), (6000, 1, 3.0)])
 def test_far_field_cell_expansions_match_chunks(env, orc, N, M, spacing):
     """Cells of four consecutive sorted chunks carry an expansion translated
     from their chunks'; a target far from a whole cell takes it once instead of
